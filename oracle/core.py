@@ -1,0 +1,109 @@
+"""ctypes binding of ``ht_oracle.c`` (test infrastructure only).
+
+Every function takes and returns numpy arrays; matrices are passed to C as
+column-major FP64 copies, so callers' arrays are never modified.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ht_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_BUILD, "liboracle.so")
+_lib = None
+
+
+def oracle_lib_path():
+    return _LIB
+
+
+def build_oracle(force=True):
+    """Compile ht_oracle.c with gcc (plain C, -O2, strict IEEE: no -ffast-math)."""
+    os.makedirs(_BUILD, exist_ok=True)
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                           "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build_oracle()
+    lib = ctypes.CDLL(_LIB)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.orc_house.restype = ctypes.c_double
+    lib.orc_house.argtypes = [ctypes.c_int, dp, dp, dp]
+    lib.orc_basic_ht.restype = ctypes.c_int
+    lib.orc_basic_ht.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, ctypes.c_uint64]
+    lib.orc_ms_ht.restype = None
+    lib.orc_ms_ht.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
+    lib.orc_normal.restype = ctypes.c_double
+    lib.orc_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _fcopy(M):
+    return np.array(M, dtype=np.float64, order="F", copy=True)
+
+
+def house(x):
+    """Householder reflector of Golub & Van Loan Alg. 5.1.1 (cited in Lemma 2.1).
+
+    Returns (v, beta, alpha) with v[0] = 1 and (I - beta v v^T) x = alpha e1,
+    alpha = ||x||_2.
+    """
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    v = np.zeros_like(x)
+    beta = ctypes.c_double(0.0)
+    alpha = lib.orc_house(len(x), _ptr(x), _ptr(v), ctypes.byref(beta))
+    return v, beta.value, alpha
+
+
+def basic_ht(A, B, ncols=None, seed=0):
+    """Algorithm 2 (BasicHouseHT, Appendix A).  Returns (H, T, Q, Z, n_perturbed).
+
+    ``ncols`` limits the reduction to the first ncols columns (default n-2);
+    after c columns, H[:, :c], T[:, :c+1], Q[:, :c+1] and Z[:, :c+1] are final.
+    """
+    lib = _load()
+    n = A.shape[0]
+    H, T = _fcopy(A), _fcopy(B)
+    Q = np.zeros((n, n), order="F")
+    Z = np.zeros((n, n), order="F")
+    if ncols is None:
+        ncols = max(n - 2, 0)
+    npert = lib.orc_basic_ht(n, _ptr(H), _ptr(T), _ptr(Q), _ptr(Z), int(ncols), int(seed))
+    return H, T, Q, Z, npert
+
+
+def ms_ht(A, B, ncols=None):
+    """Moler-Stewart Givens HT reduction.  Returns (H, T, Q, Z)."""
+    lib = _load()
+    n = A.shape[0]
+    H, T = _fcopy(A), _fcopy(B)
+    Q = np.zeros((n, n), order="F")
+    Z = np.zeros((n, n), order="F")
+    if ncols is None:
+        ncols = max(n - 2, 0)
+    lib.orc_ms_ht(n, _ptr(H), _ptr(T), _ptr(Q), _ptr(Z), int(ncols))
+    return H, T, Q, Z
+
+
+def normal(seed, counter):
+    """N(0,1) number `counter` of stream `seed` (splitmix64 + Box-Muller)."""
+    return _load().orc_normal(int(seed), int(counter))

@@ -1,0 +1,248 @@
+"""Pins for the CPU oracle, each against something other than the oracle itself.
+
+* house: the reflector's defining property against numpy's norm, exact edge
+  cases, extreme magnitudes (Sec. 2.1, Golub & Van Loan Alg. 5.1.1).
+* Algorithm 2 (BasicHouseHT, Appendix A) against Moler-Stewart (a different
+  algorithm, Givens-based, no solves) and against the Krylov-basis
+  characterisation of the HT form for tiny n (no algorithm at all).
+* Special cases that reduce to library routines: B = I gives the Householder
+  Hessenberg form of A (scipy.linalg.hessenberg); an HT input is returned up
+  to signs.
+* Spectrum: eig(H, T) = eig(A, B) (scipy.linalg.eigvals).
+* Theorem A.1 and its corollary: structure, orthogonality, backward error.
+* Lemma 2.1: the opposite reflector leaves a column 2:n of size
+  O(n u ||B||_F) before it is zeroed.
+* Remark 2.2 / Sec. 3.2.1: singular B (exact zero pivots) still gives a
+  backward stable reduction; the ill-conditioned generator never yields
+  Inf/NaN.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import oracle
+from oracle import checks
+from paper_1710_08538_amd import inputs
+
+U = 2.0 ** -53
+
+
+# ----------------------------------------------------------------- house ---
+
+@pytest.mark.parametrize("m", [1, 2, 3, 17, 100])
+def test_house_reduces_vector(m):
+    rng = np.random.default_rng(m)
+    x = rng.standard_normal(m)
+    v, beta, alpha = oracle.house(x)
+    assert v[0] == 1.0
+    P = np.eye(m) - beta * np.outer(v, v)
+    y = P @ x
+    assert abs(alpha - np.linalg.norm(x)) <= 4 * U * np.linalg.norm(x)
+    assert abs(y[0] - alpha) <= 8 * m * U * np.linalg.norm(x)
+    assert np.abs(y[1:]).max(initial=0.0) <= 8 * m * U * np.linalg.norm(x)
+    assert np.linalg.norm(P.T @ P - np.eye(m)) <= 8 * m * U
+
+
+def test_house_edge_cases():
+    v, beta, alpha = oracle.house(np.zeros(4))
+    assert beta == 0.0 and alpha == 0.0 and list(v) == [1, 0, 0, 0]
+    v, beta, alpha = oracle.house(np.array([5.0, 0.0, 0.0]))
+    assert beta == 0.0 and alpha == 5.0
+    v, beta, alpha = oracle.house(np.array([-3.0, 0.0, 0.0]))
+    assert beta == 2.0 and alpha == 3.0
+    y = (np.eye(3) - beta * np.outer(v, v)) @ np.array([-3.0, 0.0, 0.0])
+    assert list(y) == [3.0, 0.0, 0.0]
+
+
+@pytest.mark.parametrize("scale", [1e300, 1e-300, 1e-320])
+def test_house_extreme_magnitudes(scale):
+    x = np.array([3.0, -4.0, 12.0]) * scale
+    v, beta, alpha = oracle.house(x)
+    assert np.isfinite(v).all() and np.isfinite(beta)
+    # ||(3,-4,12)|| = 13 exactly
+    assert abs(alpha / (13.0 * scale) - 1.0) < 1e-12 or scale < 1e-310
+    y = x - beta * v * (v @ x)
+    assert np.abs(y[1:]).max() <= 1e-14 * 13.0 * scale + 1e-323
+
+
+def test_normal_stream():
+    a = np.array([oracle.normal(7, i) for i in range(20000)])
+    assert abs(a.mean()) < 0.05 and abs(a.std() - 1.0) < 0.05
+    assert oracle.normal(7, 3) == oracle.normal(7, 3)
+    assert oracle.normal(7, 3) != oracle.normal(8, 3)
+
+
+# -------------------------------------------------- whole reduction pins ---
+
+def _check_inv(A, B, out, tol_scale=1.0):
+    H, T, Q, Z = out[:4]
+    inv = checks.invariants(A, B, H, T, Q, Z)
+    assert checks.invariants_ok(inv, A.shape[0]), inv
+    return inv
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 8, 16, 64])
+def test_basic_matches_moler_stewart(n):
+    A, B = inputs.random_pencil(n, seed=100 + n)
+    ref = oracle.ms_ht(A, B)
+    got = oracle.basic_ht(A, B)
+    _check_inv(A, B, ref)
+    _check_inv(A, B, got)
+    d = checks.compare(ref, got[:4], A, B)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-12, (key, d)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6])
+def test_basic_matches_krylov_characterisation(n):
+    A, B = inputs.random_pencil(n, seed=200 + n)
+    ref = checks.krylov_reference(A, B)
+    got = oracle.basic_ht(A, B)[:4]
+    d = checks.compare(ref, got, A, B)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-9, (key, d)
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_ms_matches_krylov_characterisation(n):
+    A, B = inputs.random_pencil(n, seed=300 + n)
+    ref = checks.krylov_reference(A, B)
+    got = oracle.ms_ht(A, B)
+    d = checks.compare(ref, got, A, B)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-9, (key, d)
+
+
+@pytest.mark.parametrize("n", [5, 40])
+def test_identity_B_gives_hessenberg_form(n):
+    rng = np.random.default_rng(n)
+    A = np.asfortranarray(rng.standard_normal((n, n)))
+    B = np.eye(n, order="F")
+    H, T, Q, Z, _ = oracle.basic_ht(A, B)
+    Hs, Qs = sl.hessenberg(A, calc_q=True)
+    # scipy's Householder Hessenberg reduction also fixes e1; normalise both
+    # with T = I (d_z = d_q for the library form).
+    ref = (Hs, np.eye(n), Qs, Qs)
+    d = checks.compare(ref, (H, T, Q, Z), A, B)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-12, (key, d)
+
+
+def test_already_ht_input_is_fixed_point():
+    n = 12
+    rng = np.random.default_rng(5)
+    A = np.asfortranarray(np.triu(rng.standard_normal((n, n)), -1))
+    B = np.asfortranarray(np.triu(rng.standard_normal((n, n))) + 3 * np.eye(n))
+    for H, T, Q, Z in (oracle.basic_ht(A, B)[:4], oracle.ms_ht(A, B)):
+        assert np.allclose(np.abs(Q), np.eye(n), atol=1e-13)
+        assert np.allclose(np.abs(Z), np.eye(n), atol=1e-13)
+        assert np.allclose(np.abs(H), np.abs(A), atol=1e-12)
+        assert np.allclose(np.abs(T), np.abs(B), atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_tiny_orders_are_noops(n):
+    A, B = inputs.random_pencil(n, seed=1)
+    H, T, Q, Z, _ = oracle.basic_ht(A, B)
+    assert np.array_equal(H, A) and np.array_equal(T, B)
+    assert np.array_equal(Q, np.eye(n)) and np.array_equal(Z, np.eye(n))
+
+
+@pytest.mark.parametrize("n", [8, 24, 32])
+def test_generalized_eigenvalues_preserved(n):
+    A, B = inputs.random_pencil(n, seed=400 + n)
+    H, T, Q, Z, _ = oracle.basic_ht(A, B)
+    from scipy.optimize import linear_sum_assignment
+    ev_ref = sl.eigvals(A, B)
+    ev_got = sl.eigvals(H, T)
+    dist = np.abs(ev_ref[:, None] - ev_got[None, :])
+    r, c = linear_sum_assignment(dist)
+    assert dist[r, c].max() <= 1e-8 * max(1.0, np.abs(ev_ref).max())
+
+
+@pytest.mark.parametrize("n", [64, 128, 200])
+def test_theorem_a1_invariants(n):
+    A, B = inputs.random_pencil(n, seed=n)
+    _check_inv(A, B, oracle.basic_ht(A, B))
+    _check_inv(A, B, oracle.ms_ht(A, B))
+
+
+def test_partial_reduction_prefix_is_final():
+    """After c columns, H[:, :c], T[:, :c+1], Q[:, :c+1], Z[:, :c+1] equal
+    those of the full reduction (the remaining steps never touch them)."""
+    n, c = 40, 9
+    A, B = inputs.random_pencil(n, seed=9)
+    full = oracle.basic_ht(A, B)[:4]
+    part = oracle.basic_ht(A, B, ncols=c)[:4]
+    assert np.array_equal(full[0][:, :c], part[0][:, :c])
+    assert np.array_equal(full[1][:, :c + 1], part[1][:, :c + 1])
+    assert np.array_equal(full[2][:, :c + 1], part[2][:, :c + 1])
+    assert np.array_equal(full[3][:, :c + 1], part[3][:, :c + 1])
+    ms_part = oracle.ms_ht(A, B, ncols=c)
+    d = checks.compare(ms_part, part, A, B, upto=c)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-12, (key, d)
+
+
+def test_lemma_2_1_opposite_reflector():
+    n = 60
+    rng = np.random.default_rng(3)
+    B = np.triu(rng.standard_normal((n, n))) + np.diag(rng.uniform(1, 2, n))
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    x = sl.solve_triangular(B, e1)
+    v, beta, _ = oracle.house(x)
+    C = B - np.outer(B @ v, beta * v)
+    assert np.linalg.norm(C[1:, 0]) <= 10 * n * U * np.linalg.norm(B)
+    assert abs(abs(C[0, 0]) - 1.0 / np.linalg.norm(x)) <= 1e-12 * np.linalg.norm(B)
+
+
+@pytest.mark.parametrize("kind", ["zero_diag", "zero_matrix", "zero_column"])
+def test_singular_B_stays_backward_stable(kind):
+    n = 30
+    A, B = inputs.random_pencil(n, seed=77)
+    B = B.copy(order="F")
+    if kind == "zero_diag":
+        B[4, 4] = 0.0
+        B[17, 17] = 0.0
+    elif kind == "zero_matrix":
+        B[:] = 0.0
+    else:
+        B[:, 6] = 0.0
+    H, T, Q, Z, nper = oracle.basic_ht(A, B, seed=11)
+    assert np.isfinite(H).all() and np.isfinite(T).all()
+    inv = checks.invariants(A, B, H, T, Q, Z)
+    assert inv["zeros_H"] == 0 and inv["zeros_T"] == 0
+    assert inv["orth_Q"] <= 1e-13 * n and inv["orth_Z"] <= 1e-13 * n
+    assert inv["bwd_A"] <= 1e-14 * n
+    if kind == "zero_matrix":
+        assert nper > 0 and np.count_nonzero(T) == 0
+    else:
+        assert inv["bwd_B"] <= 1e-14 * n
+
+
+@pytest.mark.parametrize("n", [64, 160])
+def test_illconditioned_generator_stays_finite(n):
+    A, B = inputs.illcond_pencil(n, seed=2)
+    out = oracle.basic_ht(A, B)
+    assert all(np.isfinite(M).all() for M in out[:4])
+    _check_inv(A, B, out)
+    _check_inv(A, B, oracle.ms_ht(A, B))
+
+
+def test_planted_mistakes_are_caught():
+    """A plausible slip in a reduction (a transposed factor, a dropped
+    reflector, a wrong sign in one update) must fail the pins above."""
+    n = 6
+    A, B = inputs.random_pencil(n, seed=606)
+    H, T, Q, Z, _ = oracle.basic_ht(A, B)
+    ref = checks.krylov_reference(A, B)
+    bad_variants = [
+        (H, T, Q.T, Z),                                   # transposed Q
+        (H, T, Q, np.eye(n)),                             # dropped right transforms
+        (H + 1e-6 * np.triu(np.ones((n, n)), 2), T, Q, Z),  # perturbed H
+    ]
+    for bad in bad_variants:
+        inv = checks.invariants(A, B, *bad)
+        d = checks.compare(ref, bad, A, B)
+        assert (not checks.invariants_ok(inv, n)) or max(d["max_H"], d["max_Q"], d["max_Z"]) > 1e-9
