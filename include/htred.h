@@ -1,0 +1,162 @@
+/*
+ * htred.h -- C ABI of the MI355X (gfx950) Householder Hessenberg-triangular
+ * reduction library, libhtred.so.
+ *
+ * Method: Bujanovic, Karlsson, Kressner, "A Householder-based algorithm for
+ * Hessenberg-triangular reduction" (HouseHT).  Given A and an upper
+ * triangular B (both n x n), the library computes orthogonal Q and Z with
+ *     H = Q^T A Z   upper Hessenberg,     T = Q^T B Z   upper triangular
+ * (problem statement of Sec. 1 and the opening of Sec. 3; Algorithm 1).
+ * Columns of A are reduced by Householder reflectors from the left; the
+ * matching column of B is reduced by an opposite reflector from the right,
+ * built from a solve with B (Sec. 2.2, Lemma 2.1).  Reflectors are gathered
+ * in panels of nb columns with B kept in the factored form of eq. (tildeB)
+ * (Sec. 3.2) and then absorbed into A, B, Q, Z as block-reflector products
+ * (Sec. 3.3).
+ *
+ * Conventions for every entry point:
+ *   - matrices are FP64, column-major, on the device (HIP device pointers);
+ *     leading dimensions must be >= max(1, n);
+ *   - the caller owns every buffer; the library keeps no pointer after the
+ *     call returns;
+ *   - work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *     the default stream).  Unless stated otherwise a call returns after
+ *     its work is enqueued; host-side results (stats) force a stream sync;
+ *   - return value 0 is success; a negative value -i flags argument i as
+ *     invalid (LAPACK INFO style, 1-based argument position); positive
+ *     values are HT_ERR_* codes below.  ht_strerror() names every code.
+ */
+#ifndef HTRED_H
+#define HTRED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Positive error codes. */
+#define HT_OK              0
+#define HT_ERR_HIP         1  /* a HIP runtime call failed */
+#define HT_ERR_WORKSPACE   2  /* workspace too small or misaligned */
+#define HT_ERR_NONFINITE   3  /* NaN or Inf found in A or B on entry */
+#define HT_ERR_UNSUPPORTED 4  /* option combination not implemented */
+#define HT_ERR_NOLIB       5  /* device code for this GPU is missing */
+
+/* How Q and Z are produced. */
+typedef enum {
+    HT_QZ_IDENTITY = 0,   /* Q, Z are set to I on entry (Sec. 3 opening) */
+    HT_QZ_ACCUMULATE = 1, /* Q <- Q_in * Q, Z <- Z_in * Z */
+    HT_QZ_NONE = 2        /* not computed (pointer may be NULL) */
+} ht_qz_mode;
+
+/* Arithmetic of the trailing block-reflector updates (absorption, Sec. 3.3).
+ * Panel reduction, solves and factorisations are always native FP64. */
+typedef enum {
+    HT_PREC_FP64 = 0,        /* native FP64 (MFMA) */
+    HT_PREC_SPLIT_BF16 = 1,  /* FP64 emulated with BF16 slices, FP32 accumulate */
+    HT_PREC_SPLIT_FP8 = 2    /* FP64 emulated with FP8-E4M3 slices */
+} ht_precision;
+
+typedef struct {
+    int32_t struct_size;     /* = sizeof(ht_options); checked */
+    int32_t nb;              /* panel width (number of reflectors per absorption);
+                                0 = default 64.  Must be 1..128. */
+    int32_t max_ir;          /* iterative-refinement steps before a panel is cut
+                                short (Sec. 3.2.2 c): default 10 */
+    int32_t qmode;           /* ht_qz_mode for Q */
+    int32_t zmode;           /* ht_qz_mode for Z */
+    int32_t prec;            /* ht_precision */
+    int32_t n_slices;        /* slices per operand for split precision; 0 = auto */
+    int32_t flags;           /* HT_FLAG_* bits */
+    double  ir_tol_factor;   /* IR stops when ||r||/||x|| <= f * u * ||B||_F;
+                                default 2.0 (Sec. 2.3) */
+    uint64_t seed;           /* stream for the zero-diagonal perturbation rho
+                                (Sec. 3.2.1) */
+} ht_options;
+
+/* flags */
+#define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs) */
+
+typedef struct {
+    int64_t columns;          /* columns reduced */
+    int64_t cols_extra_ir;    /* columns that needed at least one IR step */
+    int64_t ir_steps;         /* total IR correction steps */
+    int64_t ir_failures;      /* columns whose IR did not converge (panel cut) */
+    int64_t absorptions;      /* number of absorptions (panels) */
+    int64_t scaled_solves;    /* solves that needed overflow rescaling */
+    double  flops;            /* flops executed, counted from launch shapes */
+    double  ms_total;         /* wall time of the call (ms), host clock */
+} ht_stats;
+
+/* Fills *opt with the defaults listed above.  Returns 0. */
+int ht_default_options(ht_options *opt);
+
+/* Device workspace (bytes) ht_reduce needs for order n with these options
+ * (opt may be NULL for the defaults). */
+size_t ht_workspace_size(int64_t n, const ht_options *opt);
+
+/*
+ * ht_reduce -- HouseHT reduction of one pencil (Algorithm 1 with the panel
+ * reduction of Sec. 3.2 and the absorption of Sec. 3.3).
+ *
+ *   A  (in/out)  n x n, lda:  A on entry, H on exit (exact zeros below the
+ *                first subdiagonal).
+ *   B  (in/out)  n x n, ldb:  upper triangular B on entry (the strictly lower
+ *                triangle is ignored), T on exit (exact zeros below the
+ *                diagonal).  An exactly zero (or subnormal) diagonal entry
+ *                met by a solve is replaced by 2 u rho ||B||_F, rho ~ N(0,1)
+ *                (Sec. 3.2.1, Remark 2.2): T is then exact for B + Delta_0.
+ *   Q, Z (out or in/out per qmode/zmode)  n x n, ldq/ldz.
+ *   opt   options or NULL for defaults.
+ *   stats NULL, or receives counters; a non-NULL stats makes the call wait
+ *         for the stream.
+ *   workspace / ws_bytes: NULL/0 lets the library allocate (and free)
+ *         device memory itself; otherwise at least ht_workspace_size bytes,
+ *         256-byte aligned, owned by the caller.
+ *   stream hipStream_t (void*), NULL = default stream.
+ *
+ * The call synchronises `stream` once per column whose solve needs
+ * iterative refinement and once per reflector pair to read the refinement
+ * verdict, so it is not graph-capturable; ht_reduce_batched is.
+ * Results are deterministic: no floating-point atomics are used.
+ */
+int ht_reduce(double *A, double *B, double *Q, double *Z, int64_t n,
+              int64_t lda, int64_t ldb, int64_t ldq, int64_t ldz,
+              const ht_options *opt, ht_stats *stats,
+              void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * ht_reduce_batched -- independent HT reductions of `batch` small pencils in
+ * one persistent launch (HT reduction inside deflation windows, Sec. 1).
+ *
+ *   n_dev[i]  order of pencil i (device int32 array), 0 <= n <= 512;
+ *   A_dev, B_dev, Q_dev, Z_dev: device arrays of device pointers, pencil i
+ *             column-major with leading dimension ld_dev[i] (device int32);
+ *             A, B in/out as in ht_reduce, Q and Z set (identity start);
+ *   info_dev  device int32 array: 0 per success;
+ *   nmax      host-side upper bound of n_dev (sizes the launch);
+ *   opt       as in ht_reduce (nb, max_ir, ir_tol_factor, seed used).
+ * No host synchronisation and no allocation inside: the call can be
+ * captured in a hipGraph.  workspace must hold
+ * ht_batched_workspace_size(batch, nmax, opt) bytes.
+ */
+size_t ht_batched_workspace_size(int32_t batch, int32_t nmax, const ht_options *opt);
+int ht_reduce_batched(int32_t batch, const int32_t *n_dev,
+                      double *const *A_dev, double *const *B_dev,
+                      double *const *Q_dev, double *const *Z_dev,
+                      const int32_t *ld_dev, int32_t *info_dev, int32_t nmax,
+                      const ht_options *opt, void *workspace, size_t ws_bytes,
+                      void *stream);
+
+/* Human-readable name of a return code. */
+const char *ht_strerror(int code);
+
+/* Library version string, e.g. "htred 0.1 gfx950". */
+const char *ht_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTRED_H */

@@ -1,0 +1,341 @@
+// ht_blas.hip -- dense FP64 building blocks (GEMM, GEMV, TRMV, norms, copies)
+// used by the HouseHT driver.  All kernels are deterministic (fixed
+// reduction order, no floating-point atomics).
+#include "ht_device.h"
+#include "ht_internal.h"
+
+namespace htk {
+
+static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// GEMM: C = alpha op(A) op(B) + beta C.  64x64 output tile per 256-thread
+// workgroup, each thread a 4x4 micro-tile, K staged through LDS in 16-wide
+// slices.
+// ---------------------------------------------------------------------------
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
+                                              const double* __restrict__ A, int lda,
+                                              const double* __restrict__ B, int ldb,
+                                              double beta, double* __restrict__ C, int ldc) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int ti = tid & 15, tj = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+
+  for (int k0 = 0; k0 < k; k0 += 16) {
+#pragma unroll
+    for (int rep = 0; rep < 4; ++rep) {
+      const int e = tid + rep * 256;
+      int kk, i;
+      if (!TA) { i = e & 63; kk = e >> 6; } else { kk = e & 15; i = e >> 4; }
+      double v = 0.0;
+      if (i0 + i < m && k0 + kk < k)
+        v = TA ? A[(size_t)(k0 + kk) + (size_t)(i0 + i) * lda]
+               : A[(size_t)(i0 + i) + (size_t)(k0 + kk) * lda];
+      As[kk][i] = v;
+      int jj;
+      if (!TB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
+      v = 0.0;
+      if (j0 + jj < n && k0 + kk < k)
+        v = TB ? B[(size_t)(j0 + jj) + (size_t)(k0 + kk) * ldb]
+               : B[(size_t)(k0 + kk) + (size_t)(j0 + jj) * ldb];
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[kk][ti + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tj + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + ti + 16 * r;
+    if (i >= m) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + tj + 16 * c;
+      if (j >= n) continue;
+      double* p = C + (size_t)i + (size_t)j * ldc;
+      *p = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * *p);
+    }
+  }
+}
+
+void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k, double alpha,
+          const double* A, int lda, const double* B, int ldb, double beta, double* C,
+          int ldc) {
+  if (m <= 0 || n <= 0) return;
+  if (k <= 0) {
+    // C = beta C
+    if (beta == 1.0) return;
+    dim3 grid(cdiv(m, 64), cdiv(n, 64));
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, m, n, 0, 0.0, A,
+                       lda, B, ldb, beta, C, ldc);
+    return;
+  }
+  dim3 grid(cdiv(m, 64), cdiv(n, 64));
+  if (!transA && !transB)
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else if (transA && !transB)
+    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else if (!transA && transB)
+    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else
+    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+// ---------------------------------------------------------------------------
+// GEMV y = alpha X x + beta y.  Column chunks of KC columns per workgroup
+// write partial sums; a second kernel adds them in chunk order.
+// ---------------------------------------------------------------------------
+constexpr int KC = 1024;
+
+__global__ __launch_bounds__(256) void k_gemv_n_part(int m, int k, const double* __restrict__ X,
+                                                     int ldx, const double* __restrict__ x,
+                                                     int incx, double* __restrict__ part) {
+  __shared__ double xs[KC];
+  const int c0 = blockIdx.y * KC;
+  const int kc = min(KC, k - c0);
+  for (int t = threadIdx.x; t < kc; t += 256) xs[t] = x[(size_t)(c0 + t) * incx];
+  __syncthreads();
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= m) return;
+  const double* p = X + (size_t)row + (size_t)c0 * ldx;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = 0;
+  for (; c + 4 <= kc; c += 4) {
+    s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+    s1 = fma(p[(size_t)(c + 1) * ldx], xs[c + 1], s1);
+    s2 = fma(p[(size_t)(c + 2) * ldx], xs[c + 2], s2);
+    s3 = fma(p[(size_t)(c + 3) * ldx], xs[c + 3], s3);
+  }
+  for (; c < kc; ++c) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+  part[(size_t)blockIdx.y * m + row] = (s0 + s1) + (s2 + s3);
+}
+
+__global__ __launch_bounds__(256) void k_gemv_n_fin(int m, int nch, const double* __restrict__ part,
+                                                    double alpha, double beta, double* y) {
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= m) return;
+  double s = 0.0;
+  for (int c = 0; c < nch; ++c) s += part[(size_t)c * m + row];
+  y[row] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[row]);
+}
+
+void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
+            const double* x, int incx, double beta, double* y, double* partials) {
+  if (m <= 0) return;
+  if (k <= 0) {
+    hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, 0, partials,
+                       alpha, beta, y);
+    return;
+  }
+  const int nch = cdiv(k, KC);
+  hipLaunchKernelGGL(k_gemv_n_part, dim3(cdiv(m, 256), nch), dim3(256), 0, st, m, k, X, ldx, x,
+                     incx, partials);
+  hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nch, partials, alpha,
+                     beta, y);
+}
+
+// ---------------------------------------------------------------------------
+// GEMV^T z = alpha X^T x + beta z: workgroup (column c, row chunk) partials.
+// ---------------------------------------------------------------------------
+constexpr int RC = 4096;
+
+__global__ __launch_bounds__(256) void k_gemv_t_part(int m, int k, const double* __restrict__ X,
+                                                     int ldx, const double* __restrict__ x,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  const int r0 = blockIdx.y * RC;
+  const int r1 = min(m, r0 + RC);
+  const double* p = X + (size_t)c * ldx;
+  double s = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += 256) s = fma(p[r], x[r], s);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * k + c] = s;
+}
+
+__global__ void k_gemv_t_fin(int k, int nch, const double* __restrict__ part, double alpha,
+                             double beta, double* z) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double s = 0.0;
+  for (int i = 0; i < nch; ++i) s += part[(size_t)i * k + c];
+  z[c] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * z[c]);
+}
+
+void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
+            const double* x, double beta, double* z, double* partials) {
+  if (k <= 0) return;
+  const int nch = m > 0 ? cdiv(m, RC) : 0;
+  if (nch > 0)
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(k, nch), dim3(256), 0, st, m, k, X, ldx, x, partials);
+  hipLaunchKernelGGL(k_gemv_t_fin, dim3(cdiv(k, 128)), dim3(128), 0, st, k, nch, partials, alpha,
+                     beta, z);
+}
+
+// ---------------------------------------------------------------------------
+// TRMV y = B x, B upper triangular: like GEMV, chunks left of the row block
+// are skipped (they write zeros) and only entries with col >= row are read.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trmv_part(int m, const double* __restrict__ B, int ldb,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ part) {
+  __shared__ double xs[KC];
+  const int c0 = blockIdx.y * KC;
+  const int kc = min(KC, m - c0);
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  const int rowblk_end = min(m, (int)(blockIdx.x * 256 + 256));
+  if (c0 + kc <= (int)(blockIdx.x * 256)) {  // chunk entirely below the diagonal
+    if (row < m) part[(size_t)blockIdx.y * m + row] = 0.0;
+    return;
+  }
+  (void)rowblk_end;
+  for (int t = threadIdx.x; t < kc; t += 256) xs[t] = x[c0 + t];
+  __syncthreads();
+  if (row >= m) return;
+  const double* p = B + (size_t)row + (size_t)c0 * ldb;
+  double s0 = 0.0, s1 = 0.0;
+  int cstart = max(0, row - c0);
+  int c = cstart;
+  for (; c + 2 <= kc; c += 2) {
+    s0 = fma(p[(size_t)c * ldb], xs[c], s0);
+    s1 = fma(p[(size_t)(c + 1) * ldb], xs[c + 1], s1);
+  }
+  for (; c < kc; ++c) s0 = fma(p[(size_t)c * ldb], xs[c], s0);
+  part[(size_t)blockIdx.y * m + row] = s0 + s1;
+}
+
+void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x, double* y,
+                double* partials) {
+  if (m <= 0) return;
+  const int nch = cdiv(m, KC);
+  hipLaunchKernelGGL(k_trmv_part, dim3(cdiv(m, 256), nch), dim3(256), 0, st, m, B, ldb, x,
+                     partials);
+  hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nch, partials, 1.0,
+                     0.0, y);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise helpers.
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double* x, int m, double v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] = v;
+}
+void fill(hipStream_t st, double* x, int m, double v) {
+  if (m > 0) hipLaunchKernelGGL(k_fill, dim3(cdiv(m, 256)), dim3(256), 0, st, x, m, v);
+}
+
+__global__ void k_copy(double* d, const double* s, int m) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) d[i] = s[i];
+}
+void copy(hipStream_t st, double* dst, const double* src, int m) {
+  if (m > 0) hipLaunchKernelGGL(k_copy, dim3(cdiv(m, 256)), dim3(256), 0, st, dst, src, m);
+}
+
+__global__ void k_copy_mat(int m, int n, const double* s, int lds, double* d, int ldd) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < m && j < n) d[(size_t)i + (size_t)j * ldd] = s[(size_t)i + (size_t)j * lds];
+}
+void copy_mat(hipStream_t st, int m, int n, const double* src, int lds, double* dst, int ldd) {
+  if (m > 0 && n > 0)
+    hipLaunchKernelGGL(k_copy_mat, dim3(cdiv(m, 256), n), dim3(256), 0, st, m, n, src, lds, dst, ldd);
+}
+
+__global__ void k_set_identity(double* X, int n, int ld) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < n) X[(size_t)i + (size_t)j * ld] = (i == j) ? 1.0 : 0.0;
+}
+void set_identity(hipStream_t st, double* X, int n, int ld) {
+  if (n > 0) hipLaunchKernelGGL(k_set_identity, dim3(cdiv(n, 256), n), dim3(256), 0, st, X, n, ld);
+}
+
+// zero entries with row > col + offset (offset 0: strictly lower; 1: below
+// the first subdiagonal)
+__global__ void k_zero_lower(double* X, int n, int ld, int offset) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < n && i > j + offset) X[(size_t)i + (size_t)j * ld] = 0.0;
+}
+void zero_lower(hipStream_t st, double* X, int n, int ld, int offset) {
+  if (n > 0) hipLaunchKernelGGL(k_zero_lower, dim3(cdiv(n, 256), n), dim3(256), 0, st, X, n, ld, offset);
+}
+
+__global__ void k_zero_mat(double* X, int m, int n, int ld) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y;
+  if (i < m && j < n) X[(size_t)i + (size_t)j * ld] = 0.0;
+}
+void zero_mat(hipStream_t st, double* X, int m, int n, int ld) {
+  if (m > 0 && n > 0) hipLaunchKernelGGL(k_zero_mat, dim3(cdiv(m, 256), n), dim3(256), 0, st, X, m, n, ld);
+}
+
+__global__ void k_scale_pow2(double* x, int m, const int* e, int sign) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] = ldexp(x[i], sign * e[0]);
+}
+void scale_pow2(hipStream_t st, double* x, int m, const int* e_dev, int sign) {
+  if (m > 0) hipLaunchKernelGGL(k_scale_pow2, dim3(cdiv(m, 256)), dim3(256), 0, st, x, m, e_dev, sign);
+}
+
+// Frobenius norm: per-column-chunk scaled sums of squares, then a final pass.
+__global__ __launch_bounds__(256) void k_fro_part(int m, int n, const double* X, int ld,
+                                                  double* part) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    double v = X[(size_t)i + (size_t)j * ld];
+    s = fma(v, v, s);
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[j] = s;
+}
+__global__ __launch_bounds__(256) void k_fro_fin(int n, const double* part, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) s += part[j];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+void fro_norm(hipStream_t st, int m, int n, const double* X, int ld, double* out,
+              double* partials) {
+  if (m <= 0 || n <= 0) { fill(st, out, 1, 0.0); return; }
+  hipLaunchKernelGGL(k_fro_part, dim3(n), dim3(256), 0, st, m, n, X, ld, partials);
+  hipLaunchKernelGGL(k_fro_fin, dim3(1), dim3(256), 0, st, n, partials, out);
+}
+
+int num_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
+}  // namespace htk

@@ -1,0 +1,93 @@
+// ht_device.h -- device-side helpers shared by the HIP kernels of libhtred.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace htk {
+
+constexpr double kUnitRoundoff = 0x1.0p-53;
+constexpr double kBig = 0x1.0p600;      // rescale threshold for solves
+constexpr double kShrink = 0x1.0p-600;  // 1 / kBig
+constexpr int kShrinkExp = 600;
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-wide sum over blockDim.x threads (multiple of 64, <= 1024); every
+// thread receives the result.  `sh` must hold blockDim.x/64 doubles; the
+// summation order is fixed, so results are deterministic.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s = fmax(s, sh[i]);
+  return s;
+}
+
+// Counter-based N(0,1) numbers: splitmix64 (Steele, Lea, Flood 2014) feeding
+// Box-Muller; used for the zero-diagonal perturbation rho.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double normal_draw(uint64_t seed, uint64_t counter) {
+  uint64_t a = splitmix64(seed ^ splitmix64(2 * counter));
+  uint64_t b = splitmix64(seed ^ splitmix64(2 * counter + 1));
+  double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53;
+  double u2 = ((double)(b >> 11)) * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// Reflector coefficients from alpha (pivot) and the scaled norm of the
+// remaining entries (LAPACK dlarfg convention): (I - tau v v^T) x = beta e1,
+// beta = -sign(alpha) ||x||, v = x / (alpha - beta) below the pivot.
+struct Refl { double tau, beta, scal; };
+__device__ __forceinline__ Refl make_refl(double alpha, double xnorm) {
+  Refl r;
+  if (xnorm == 0.0) { r.tau = 0.0; r.beta = alpha; r.scal = 0.0; return r; }
+  double nrm = hypot(alpha, xnorm);
+  r.beta = (alpha >= 0.0) ? -nrm : nrm;
+  r.tau = (r.beta - alpha) / r.beta;
+  r.scal = 1.0 / (alpha - r.beta);
+  return r;
+}
+
+}  // namespace htk

@@ -1,0 +1,654 @@
+// ht_driver.hip -- host driver of the HouseHT reduction and the C ABI.
+//
+// Algorithm 1 (HouseHT) with the panel reduction of Sec. 3.2 and the
+// absorption of Sec. 3.3, on one GPU.  Indices are 0-based: a panel starts
+// at column s, its reflectors have support rows/columns >= s+1, and the
+// "local" frame of a panel is rows/columns s+1 .. n-1 (L = n-s-1 of them).
+// U, V, Y are stored in that local frame (local row r <-> global row s+1+r).
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "../../include/htred.h"
+#include "ht_internal.h"
+
+using namespace htk;
+
+namespace {
+
+hipError_t g_last_hip = hipSuccess;
+
+// Block structure of the trailing m' = n-j-1 rows/columns for an absorption
+// with k reflectors.  Blocks b_0 = [0, p) and b_t = [p+(t-1)k, p+tk),
+// t = 1..T (Remark 3.3: the first window has p+k rows, the others 2k; p = 0
+// only when m' = k).  The left side mirrors this from the bottom:
+// d_0 = [m'-p, m'), d_t = [m'-p-tk, m'-p-(t-1)k).
+struct Blocks {
+  int p, T, m, k;
+  int rws(int t) const { return t == 1 ? 0 : p + (t - 2) * k; }  // right window t
+  int rwe(int t) const { return p + t * k; }
+  int rbs(int t) const { return t == 0 ? 0 : p + (t - 1) * k; }  // start of b_t
+  int ds(int t) const { return t == 0 ? m - p : m - p - t * k; }  // d_t
+  int de(int t) const { return t == 0 ? m : m - p - (t - 1) * k; }
+  int lws(int t) const { return ds(t); }                           // left window t
+  int lwe(int t) const { return de(t - 1); }
+};
+
+Blocks make_blocks(int mprime, int k) {
+  Blocks b;
+  b.m = mprime;
+  b.k = k;
+  if (mprime == k) { b.p = 0; b.T = 1; return b; }
+  const int q = mprime % k;
+  b.p = q ? q : k;
+  b.T = (mprime - b.p) / k;
+  return b;
+}
+
+struct Work {
+  int n = 0, nb = 0;
+  double *U, *V, *Y, *S, *T, *Ucp;
+  double *acol_save, *ctil, *ysol, *dsol, *wv, *w2, *rv;
+  double *tk, *tk2, *gk, *Ucat, *Kt, *Kt2, *P, *Wk;
+  double* partials;
+  double* pool[4][2];  // chain transform pools: [chain][V or W]
+  double* Gws;
+  double* dscal;       // [0] tau_u, [1] beta_u, [2] normB, [3..4] IR norms, [5] tau_v, [6] beta_v
+  int *flags, *exps, *ints;  // ints: [1] E_rhs, [2] E_corr, [3] status, [4] fixes, [5] scaled
+  int epoch = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t layout(Work* w, int n, int nb, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t doubles) -> double* {
+    double* p = base ? (double*)(base + off) : nullptr;
+    off += align256(doubles * 8);
+    return p;
+  };
+  const size_t N = (size_t)std::max(n, 1), K = (size_t)nb;
+  w->n = n;
+  w->nb = nb;
+  w->U = take(N * K);
+  w->V = take(N * K);
+  w->Y = take(N * K);
+  w->Ucp = take(N * K);
+  w->S = take(K * K);
+  w->T = take(K * K);
+  w->acol_save = take(N);
+  w->ctil = take(N);
+  w->ysol = take(N);
+  w->dsol = take(N);
+  w->wv = take(N);
+  w->w2 = take(N);
+  w->rv = take(N);
+  w->tk = take(4 * K);
+  w->tk2 = take(4 * K);
+  w->gk = take(4 * K);
+  w->Ucat = take(2 * K * K);
+  w->Kt = take(N * K);
+  w->Kt2 = take(N * K);
+  w->P = take(N * 2 * K);
+  w->Wk = take(N * K);
+  w->partials = take(std::max<size_t>(16 * N, 64 * K));
+  const size_t poolsz = 2 * N * K + 4 * K * K;
+  for (int c = 0; c < 4; ++c)
+    for (int v = 0; v < 2; ++v) w->pool[c][v] = take(poolsz);
+  w->Gws = take(2 * K * K + 8);
+  w->dscal = take(64);
+  const size_t nblk = (N + 63) / 64 + 1;
+  w->flags = (int*)take((nblk + 1) / 2 + 1);
+  w->exps = (int*)take((nblk + 1) / 2 + 1);
+  w->ints = (int*)take(32);
+  return off;
+}
+
+// Chain transform t (window width <= 2k, k reflectors) of chain `ch`.
+double* tV(Work& w, int ch, int t, int k) { return w.pool[ch][0] + (size_t)t * 2 * k * k; }
+double* tW(Work& w, int ch, int t, int k) { return w.pool[ch][1] + (size_t)t * 2 * k * k; }
+
+__global__ void k_add_at(double* x, int idx, double v) { x[idx] += v; }
+__global__ void k_scale_by(double* x, int m, const double* s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] *= s[0];
+}
+__global__ void k_count_scaled(const int* E, int* counter) {
+  if (E[0] > 0) atomicAdd(counter, 1);
+}
+__global__ void k_init_ints(int* p) {
+  if (threadIdx.x < 32) p[threadIdx.x] = 0;
+}
+__global__ void k_check_finite(int m, int n, const double* X, int ld, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i < m && j < n) {
+    const double v = X[(size_t)i + (size_t)j * ld];
+    if (!isfinite(v)) atomicOr(bad, 1);
+  }
+}
+
+inline double* at(double* X, int ld, int r, int c) { return X + (size_t)r + (size_t)c * ld; }
+
+struct Ctx {
+  hipStream_t st;
+  Work* w;
+  int n, nb;
+  double *A, *B, *Q, *Z;
+  int lda, ldb, ldq, ldz;
+  bool wantQ, wantZ;
+  ht_options opt;
+  int* host_ints;  // pinned mirror of w->ints
+  double flops = 0.0;
+  int64_t cols_extra_ir = 0, ir_steps = 0, ir_failures = 0, absorptions = 0, columns = 0;
+};
+
+// X(0:rows, window) <- X (I - V W^T), window width wdt, k reflectors.
+void right_apply(Ctx& c, double* X, int ld, int rows, int wdt, int k, const double* Vf,
+                 const double* Wf) {
+  if (rows <= 0 || wdt <= 0 || k <= 0) return;
+  gemm(c.st, false, false, rows, k, wdt, 1.0, X, ld, Vf, wdt, 0.0, c.w->P, c.n);
+  gemm(c.st, false, true, rows, wdt, k, -1.0, c.w->P, c.n, Wf, wdt, 1.0, X, ld);
+  c.flops += 4.0 * rows * (double)wdt * k;
+}
+
+// X(window, 0:ncols) <- (I - V W^T)^T X = X - W (V^T X).
+void left_apply(Ctx& c, double* X, int ld, int ncols, int wdt, int k, const double* Vf,
+                const double* Wf) {
+  if (ncols <= 0 || wdt <= 0 || k <= 0) return;
+  gemm(c.st, true, false, k, ncols, wdt, 1.0, Vf, wdt, X, ld, 0.0, c.w->P, k);
+  gemm(c.st, false, false, wdt, ncols, k, -1.0, Wf, wdt, c.w->P, k, 1.0, X, ld);
+  c.flops += 4.0 * ncols * (double)wdt * k;
+}
+
+// Window list of a chain: (start, width, nrefl, slot) in application order.
+struct Win { int a, wdt, k, slot; };
+
+std::vector<Win> right_windows(const Blocks& bl, int chain) {
+  std::vector<Win> v;
+  if (chain == 0) {  // Q^_1 .. Q^_T (QL of V2), applied first to last
+    for (int t = 1; t <= bl.T; ++t) v.push_back({bl.rws(t), bl.rwe(t) - bl.rws(t), bl.k, t});
+  } else {           // RQ restore G_T .. G_1, G_0
+    for (int t = bl.T; t >= 1; --t) v.push_back({bl.rws(t), bl.rwe(t) - bl.rws(t), bl.k, t});
+    if (bl.p > 0) v.push_back({0, bl.p, bl.p, 0});
+  }
+  return v;
+}
+
+std::vector<Win> left_windows(const Blocks& bl, int chain) {
+  std::vector<Win> v;
+  if (chain == 2) {  // Q~_1 .. Q~_T (QR of U2, bottom to top)
+    for (int t = 1; t <= bl.T; ++t) v.push_back({bl.lws(t), bl.lwe(t) - bl.lws(t), bl.k, t});
+  } else {           // QR restore H_T .. H_1, H_0
+    for (int t = bl.T; t >= 1; --t) v.push_back({bl.lws(t), bl.lwe(t) - bl.lws(t), bl.k, t});
+    if (bl.p > 0) v.push_back({bl.ds(0), bl.p, bl.p, 0});
+  }
+  return v;
+}
+
+// Right sweep of a chain over X(0:rows, j+1 : n).  For an upper triangular
+// X (B), rows below a window's last column are zero and are skipped.
+void sweep_right(Ctx& c, double* X, int ld, int rows, bool tri, int j, const Blocks& bl,
+                 int chain) {
+  for (const Win& wn : right_windows(bl, chain)) {
+    const int r = tri ? std::min(rows, j + 1 + wn.a + wn.wdt) : rows;
+    right_apply(c, at(X, ld, 0, j + 1 + wn.a), ld, r, wn.wdt, wn.k, tV(*c.w, chain, wn.slot, bl.k),
+                tW(*c.w, chain, wn.slot, bl.k));
+  }
+}
+
+// Left sweep of a chain over rows j+1.. of X, columns [c0, n).  With
+// `tri`, columns left of a window's first row are zero and skipped.
+void sweep_left(Ctx& c, double* X, int ld, int c0, bool tri, int j, const Blocks& bl, int chain) {
+  for (const Win& wn : left_windows(bl, chain)) {
+    const int cs = tri ? std::max(c0, j + 1 + wn.a) : c0;
+    left_apply(c, at(X, ld, j + 1 + wn.a, cs), ld, c.n - cs, wn.wdt, wn.k,
+               tV(*c.w, chain, wn.slot, bl.k), tW(*c.w, chain, wn.slot, bl.k));
+  }
+}
+
+// Q(:, j+1 : n) <- Q * (chain transforms in order).
+void sweep_cols_right(Ctx& c, double* X, int ld, int rows, int j, const Blocks& bl, int chain) {
+  for (const Win& wn : left_windows(bl, chain))
+    right_apply(c, at(X, ld, 0, j + 1 + wn.a), ld, rows, wn.wdt, wn.k,
+                tV(*c.w, chain, wn.slot, bl.k), tW(*c.w, chain, wn.slot, bl.k));
+}
+
+int sync_status(Ctx& c) {
+  (void)hipMemcpyAsync(c.host_ints, c.w->ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c.st);
+  (void)hipStreamSynchronize(c.st);
+  return c.host_ints[3];
+}
+
+// ---------------------------------------------------------------------------
+// Factored solve (Sec. 3.2.2 c, steps 1-3): ctil <- (I - U S U^T) ctil;
+// B ytil = 2^{-E} ctil; y <- (I - V T V^T)^T ytil.  nu = reflectors in U.
+// ---------------------------------------------------------------------------
+void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, int* Eout) {
+  Work& w = *c.w;
+  const int L = c.n - s - 1, n = c.n;
+  gemv_t(c.st, L, nu, 1.0, w.U, n, ctil, 0.0, w.tk, w.partials);
+  trmv_small(c.st, false, nu, w.S, c.nb, w.tk, 1.0, w.tk2);
+  gemv_n(c.st, L, nu, -1.0, w.U, n, w.tk2, 1, 1.0, ctil, w.partials);
+  const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
+  trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.exps, w.flags, ++w.epoch, Eout);
+  hipLaunchKernelGGL(k_count_scaled, dim3(1), dim3(1), 0, c.st, Eout, w.ints + 5);
+  if (kk > 0) {
+    gemv_t(c.st, L, kk, 1.0, w.V, n, ysol, 0.0, w.tk, w.partials);
+    trmv_small(c.st, true, kk, w.T, c.nb, w.tk, 1.0, w.tk2);
+    gemv_n(c.st, L, kk, -1.0, w.V, n, w.tk2, 1, 1.0, ysol, w.partials);
+  }
+  c.flops += 1.0 * L * (double)L + 4.0 * L * (double)(nu + kk);
+}
+
+// Residual (Sec. 3.2.2 c): w = (I - V T V^T)[0; x]; w = B w;
+// w = (I - U S^T U^T) w; r = 2^{-E} rhs - w(kk:), rhs = e1 if NULL.
+void residual(Ctx& c, int s, int kk, const double* x, const double* rhs) {
+  Work& w = *c.w;
+  const int L = c.n - s - 1, n = c.n, m = L - kk;
+  fill(c.st, w.wv, kk, 0.0);
+  copy(c.st, w.wv + kk, x, m);
+  gemv_t(c.st, m, kk, 1.0, w.V + kk, n, x, 0.0, w.tk, w.partials);
+  trmv_small(c.st, false, kk, w.T, c.nb, w.tk, 1.0, w.tk2);
+  gemv_n(c.st, L, kk, -1.0, w.V, n, w.tk2, 1, 1.0, w.wv, w.partials);
+  const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
+  trmv_upper(c.st, L, Bp, c.ldb, w.wv, w.w2, w.partials);
+  gemv_t(c.st, L, kk + 1, 1.0, w.U, n, w.w2, 0.0, w.tk, w.partials);
+  trmv_small(c.st, true, kk + 1, w.S, c.nb, w.tk, 1.0, w.tk2);
+  gemv_n(c.st, L, kk + 1, -1.0, w.U, n, w.tk2, 1, 1.0, w.w2, w.partials);
+  ir_residual(c.st, m, w.w2 + kk, rhs, w.ints + 1, w.rv, x, w.dscal + 2, c.opt.ir_tol_factor,
+              w.ints + 3, w.dscal + 3);
+  c.flops += 1.0 * L * (double)L + 4.0 * L * (double)(2 * kk + 1);
+}
+
+// ---------------------------------------------------------------------------
+// Absorption of k left and right reflectors (Sec. 3.3).
+// ---------------------------------------------------------------------------
+void absorb(Ctx& c, int s, int k) {
+  Work& w = *c.w;
+  const int n = c.n, j = s + k, L = n - s - 1, mp = n - j - 1;
+  const Blocks bl = make_blocks(mp, k);
+  double *A = c.A, *B = c.B;
+  const int lda = c.lda, ldb = c.ldb;
+  c.absorptions++;
+
+  // (3.3.1 b) V2 = Q^_1 ... Q^_T [0; L1]: QL chain, top to bottom, in place.
+  double* V2 = w.V + k;
+  for (int t = 1; t <= bl.T; ++t) {
+    const int a = bl.rws(t), e = bl.rwe(t);
+    chain_factor(c.st, 1, e - a, k, V2 + a, n, tV(w, 0, t, k), tW(w, 0, t, k), w.Gws);
+  }
+  const double* L1 = w.V + (L - k);
+  const double* V1 = w.V;
+
+  // (3.3.2 b) U2 = Q~_1 ... Q~_T [R1; 0]: QR chain, bottom to top, on a copy
+  // (the spike update below needs the original U2).
+  copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
+  for (int t = 1; t <= bl.T; ++t) {
+    const int a = bl.lws(t), e = bl.lwe(t);
+    chain_factor(c.st, 0, e - a, k, w.Ucp + a, n, tV(w, 2, t, k), tW(w, 2, t, k), w.Gws);
+  }
+  copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
+  copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
+
+  // (3.3.1 c, d, e) right absorption.  B, Z and rows 0..s of A:
+  //   X(:, j+1:n) <- X Q^;  W = X(:, s+1:j+1) V1 + X(:, n-k:n) L1;
+  //   X(:, s+1:j+1) -= W T V1^T;  X(:, n-k:n) -= W T L1^T.
+  struct RT { double* X; int ld; int rows; bool tri; };
+  std::vector<RT> rts;
+  rts.push_back({B, ldb, n, true});
+  if (c.wantZ) rts.push_back({c.Z, c.ldz, n, false});
+  rts.push_back({A, lda, s + 1, false});
+  for (auto& rt : rts) {
+    if (rt.rows <= 0) continue;
+    sweep_right(c, rt.X, rt.ld, rt.rows, rt.tri, j, bl, 0);
+    double* Xs = at(rt.X, rt.ld, 0, s + 1);
+    double* Xe = at(rt.X, rt.ld, 0, n - k);
+    gemm(c.st, false, false, rt.rows, k, k, 1.0, Xs, rt.ld, V1, n, 0.0, w.Wk, n);
+    gemm(c.st, false, false, rt.rows, k, k, 1.0, Xe, rt.ld, L1, n, 1.0, w.Wk, n);
+    gemm(c.st, false, false, rt.rows, k, k, 1.0, w.Wk, n, w.T, c.nb, 0.0, w.P, n);
+    gemm(c.st, false, true, rt.rows, k, k, -1.0, w.P, n, V1, n, 1.0, Xs, rt.ld);
+    gemm(c.st, false, true, rt.rows, k, k, -1.0, w.P, n, L1, n, 1.0, Xe, rt.ld);
+    c.flops += 10.0 * rt.rows * (double)k * k;
+  }
+  // rows s+1..n-1 of A through Y = A V T (Sec. 3.3.1 e):
+  //   A(:, j+1:n) <- A Q^;  A(:, j) -= Y V1(k-1,:)^T;  A(:, n-k:n) -= Y L1^T.
+  sweep_right(c, at(A, lda, s + 1, 0), lda, L, false, j, bl, 0);
+  gemv_n(c.st, L, k, -1.0, w.Y, n, w.V + (k - 1), n, 1.0, at(A, lda, s + 1, j), w.partials);
+  gemm(c.st, false, true, L, k, k, -1.0, w.Y, n, L1, n, 1.0, at(A, lda, s + 1, n - k), lda);
+  c.flops += 4.0 * L * (double)k * k;
+
+  // (3.3.1 e) restore B by RQ decompositions, bottom to top: the k x (w)
+  // block of row block b_t is factored as [0 R] G_t; G_t^T is applied to
+  // the rows above it at once (the next step needs row block b_{t-1}).
+  for (const Win& wn : right_windows(bl, 1)) {
+    const int t = wn.slot;
+    const int r0 = (t == 0) ? 0 : bl.rbs(t);
+    const int kr = (t == 0) ? bl.p : k;  // rows of the block
+    double* C = at(B, ldb, j + 1 + r0, j + 1 + wn.a);
+    chain_factor_t(c.st, 1, wn.wdt, kr, C, ldb, tV(w, 1, t, k), tW(w, 1, t, k), w.Gws);
+    right_apply(c, at(B, ldb, 0, j + 1 + wn.a), ldb, j + 1 + r0, wn.wdt, kr, tV(w, 1, t, k),
+                tW(w, 1, t, k));
+  }
+  sweep_right(c, A, lda, n, false, j, bl, 1);
+  if (c.wantZ) sweep_right(c, c.Z, c.ldz, n, false, j, bl, 1);
+
+  // (3.3.2 c) spike columns s+1..j of B:
+  //   B(s+1:j+1, s+1:j+1) -= U1 S^T (U^T B(s+1:n, s+1:j+1));  B(j+1:n, s+1:j+1) = 0.
+  gemm(c.st, true, false, k, k, L, 1.0, w.U, n, at(B, ldb, s + 1, s + 1), ldb, 0.0, w.Kt, k);
+  gemm(c.st, true, false, k, k, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+  gemm(c.st, false, false, k, k, k, -1.0, w.U, n, w.Kt2, k, 1.0, at(B, ldb, s + 1, s + 1), ldb);
+  zero_mat(c.st, at(B, ldb, j + 1, s + 1), mp, k, ldb);
+  // Fact 3: columns s+1..j are now triangular; their entries below the
+  // diagonal are rounding noise of the opposite reflectors (Lemma 2.1) and are
+  // set to exact zeros, as Algorithm 2 does.
+  zero_lower(c.st, at(B, ldb, s + 1, s + 1), k, ldb, 0);
+  c.flops += 2.0 * k * (double)k * (L + 2 * k);
+
+  // (3.3.2 c, e) rows j+1..n-1: B(:, j+1:n) and A(:, j:n) <- Q~^T (.)
+  sweep_left(c, B, ldb, j + 1, true, j, bl, 2);
+  sweep_left(c, A, lda, j, false, j, bl, 2);
+  // corrections with Ucat = [U1; R1] on rows s+1..j+k:  X -= Ucat S^T (Ucat^T X)
+  {
+    const int ncb = n - j - 1, nca = n - j;
+    double* Bs = at(B, ldb, s + 1, j + 1);
+    gemm(c.st, true, false, k, ncb, 2 * k, 1.0, w.Ucat, 2 * k, Bs, ldb, 0.0, w.Kt, k);
+    gemm(c.st, true, false, k, ncb, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+    gemm(c.st, false, false, 2 * k, ncb, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, Bs, ldb);
+    double* As = at(A, lda, s + 1, j);
+    gemm(c.st, true, false, k, nca, 2 * k, 1.0, w.Ucat, 2 * k, As, lda, 0.0, w.Kt, k);
+    gemm(c.st, true, false, k, nca, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+    gemm(c.st, false, false, 2 * k, nca, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, As, lda);
+    c.flops += 10.0 * (double)k * k * (nca + ncb);
+  }
+  // (3.3.2 d) Q(:, j+1:n) <- Q Q~;  W = Q(:, s+1:j+k+1) Ucat;  Q(:, s+1:..) -= W S Ucat^T.
+  if (c.wantQ) {
+    sweep_cols_right(c, c.Q, c.ldq, n, j, bl, 2);
+    double* Qs = at(c.Q, c.ldq, 0, s + 1);
+    gemm(c.st, false, false, n, k, 2 * k, 1.0, Qs, c.ldq, w.Ucat, 2 * k, 0.0, w.Wk, n);
+    gemm(c.st, false, false, n, k, k, 1.0, w.Wk, n, w.S, c.nb, 0.0, w.P, n);
+    gemm(c.st, false, true, n, 2 * k, k, -1.0, w.P, n, w.Ucat, 2 * k, 1.0, Qs, c.ldq);
+    c.flops += 10.0 * (double)n * k * k;
+  }
+
+  // (3.3.2 f) restore B by QR decompositions, top to bottom; each H_t^T is
+  // applied at once to the columns right of its block (the next step needs
+  // them), then to A(j+1:n, j:n) and Q(:, j+1:n).
+  for (const Win& wn : left_windows(bl, 3)) {
+    const int t = wn.slot;
+    const int cs = bl.ds(t), ce = bl.de(t);  // columns d_t
+    double* M = at(B, ldb, j + 1 + wn.a, j + 1 + cs);
+    chain_factor(c.st, 0, wn.wdt, ce - cs, M, ldb, tV(w, 3, t, k), tW(w, 3, t, k), w.Gws);
+    left_apply(c, at(B, ldb, j + 1 + wn.a, j + 1 + ce), ldb, mp - ce, wn.wdt, ce - cs,
+               tV(w, 3, t, k), tW(w, 3, t, k));
+  }
+  sweep_left(c, A, lda, j, false, j, bl, 3);
+  if (c.wantQ) sweep_cols_right(c, c.Q, c.ldq, n, j, bl, 3);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1.
+// ---------------------------------------------------------------------------
+int run(Ctx& c) {
+  Work& w = *c.w;
+  const int n = c.n, nb = c.nb;
+  hipStream_t st = c.st;
+  hipLaunchKernelGGL(k_init_ints, dim3(1), dim3(64), 0, st, w.ints);
+  zero_lower(st, c.B, n, c.ldb, 0);
+  fro_norm(st, n, n, c.B, c.ldb, w.dscal + 2, w.partials);
+  if (n <= 2) return 0;
+
+  int s = 0;
+  int64_t panel = 0;
+  while (s <= n - 3) {
+    const int L = n - s - 1;
+    const int kmax = std::min(std::min(nb, n - 2 - s), L / 2);
+    fix_diagonal(st, c.B, c.ldb, s + 1, n, w.dscal + 2, c.opt.seed, (uint64_t)panel + 1,
+                 w.ints + 4);
+    zero_mat(st, w.U, L, nb, n);
+    zero_mat(st, w.V, L, nb, n);
+    zero_mat(st, w.S, nb, nb, nb);
+    zero_mat(st, w.T, nb, nb, nb);
+    int k = 0;
+    for (int kk = 0; kk < kmax; ++kk) {
+      const int j = s + kk;
+      double* acol = at(c.A, c.lda, s + 1, j);
+      copy(st, w.acol_save, acol, L);
+      // (a) update column j with the kk pending reflector pairs
+      if (kk > 0) {
+        gemv_n(st, L, kk, -1.0, w.Y, n, w.V + (kk - 1), n, 1.0, acol, w.partials);
+        gemv_t(st, L, kk, 1.0, w.U, n, acol, 0.0, w.tk, w.partials);
+        trmv_small(st, true, kk, w.S, nb, w.tk, 1.0, w.tk2);
+        gemv_n(st, L, kk, -1.0, w.U, n, w.tk2, 1, 1.0, acol, w.partials);
+        c.flops += 6.0 * L * (double)kk;
+      }
+      // (b) left reflector on A(j+1:n, j); extend S
+      const int m = L - kk;
+      double* ucol = at(w.U, n, kk, kk);
+      house(st, m, acol + kk, ucol, w.dscal + 0, w.dscal + 1, true);
+      if (kk > 0) gemv_t(st, m, kk, 1.0, w.U + kk, n, ucol, 0.0, w.tk, w.partials);
+      wy_append(st, w.S, nb, kk, w.tk, w.dscal + 0);
+      // (c) solve B~22 x = e1 via the enlarged system
+      //   ctil = (I - U S U^T) e_kk  (computed as e_kk then the update)
+      fill(st, w.ctil, L, 0.0);
+      hipLaunchKernelGGL(k_add_at, dim3(1), dim3(1), 0, st, w.ctil, kk, 1.0);
+      factored_solve(c, s, kk, kk + 1, w.ctil, w.ysol, w.ints + 1);
+      double* x = w.ysol + kk;
+      bool ok = true;
+      if (kk > 0) {
+        residual(c, s, kk, x, nullptr);
+        int status = sync_status(c);
+        int it = 0;
+        if (!status) c.cols_extra_ir++;
+        while (!status && it < c.opt.max_ir) {
+          // correction: solve B~22 d = r, x <- 2^{-E2} x + d
+          fill(st, w.ctil, kk, 0.0);
+          copy(st, w.ctil + kk, w.rv, m);
+          factored_solve(c, s, kk, kk + 1, w.ctil, w.dsol, w.ints + 2);
+          ir_update(st, m, x, w.dsol + kk, w.ints + 2, w.ints + 1);
+          residual(c, s, kk, x, nullptr);
+          status = sync_status(c);
+          ++it;
+          c.ir_steps++;
+        }
+        if (!status) ok = false;
+      }
+      if (!ok) {
+        // undo the left reflector: restore column j; U(:, kk), S(:, kk) are dropped
+        copy(st, acol, w.acol_save, L);
+        c.ir_failures++;
+        break;
+      }
+      // (d) right reflector on x; extend T and Y
+      double* vcol = at(w.V, n, kk, kk);
+      house(st, m, x, vcol, w.dscal + 5, w.dscal + 6, false);
+      if (kk > 0) gemv_t(st, m, kk, 1.0, w.V + kk, n, vcol, 0.0, w.tk, w.partials);
+      wy_append(st, w.T, nb, kk, w.tk, w.dscal + 5);
+      double* ycol = at(w.Y, n, 0, kk);
+      gemv_n(st, L, m, 1.0, at(c.A, c.lda, s + 1, j + 1), c.lda, vcol, 1, 0.0, ycol, w.partials);
+      if (kk > 0) gemv_n(st, L, kk, -1.0, w.Y, n, w.tk, 1, 1.0, ycol, w.partials);
+      hipLaunchKernelGGL(k_scale_by, dim3((L + 255) / 256), dim3(256), 0, st, ycol, L,
+                         w.dscal + 5);
+      c.flops += 2.0 * L * (double)m + 4.0 * L * (double)kk;
+      k = kk + 1;
+      c.columns++;
+    }
+    if (k == 0) return HT_ERR_HIP;  // cannot happen: the first column never refines
+    absorb(c, s, k);
+    s += k;
+    ++panel;
+  }
+  return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int ht_default_options(ht_options* opt) {
+  if (!opt) return -1;
+  memset(opt, 0, sizeof(*opt));
+  opt->struct_size = (int32_t)sizeof(ht_options);
+  opt->nb = 64;
+  opt->max_ir = 10;
+  opt->qmode = HT_QZ_IDENTITY;
+  opt->zmode = HT_QZ_IDENTITY;
+  opt->prec = HT_PREC_FP64;
+  opt->n_slices = 0;
+  opt->flags = 0;
+  opt->ir_tol_factor = 2.0;
+  opt->seed = 0x5EEDull;
+  return 0;
+}
+
+static int resolve_opts(const ht_options* in, ht_options* out) {
+  ht_default_options(out);
+  if (!in) return 0;
+  if (in->struct_size != (int32_t)sizeof(ht_options)) return -10;
+  *out = *in;
+  if (out->nb == 0) out->nb = 64;
+  if (out->nb < 1 || out->nb > 128) return -10;
+  if (out->max_ir < 0) return -10;
+  if (out->qmode < 0 || out->qmode > 2 || out->zmode < 0 || out->zmode > 2) return -10;
+  if (!(out->ir_tol_factor >= 0.0)) return -10;
+  return 0;
+}
+
+size_t ht_workspace_size(int64_t n, const ht_options* opt) {
+  ht_options o;
+  if (resolve_opts(opt, &o) != 0 || n < 0 || n > (1 << 30)) return 0;
+  Work w;
+  return layout(&w, (int)n, o.nb, nullptr) + 256;
+}
+
+int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda, int64_t ldb,
+              int64_t ldq, int64_t ldz, const ht_options* opt, ht_stats* stats, void* workspace,
+              size_t ws_bytes, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  ht_options o;
+  int rc = resolve_opts(opt, &o);
+  if (rc) return rc;
+  if (n < 0 || n > (int64_t)1 << 30) return -5;
+  const int64_t ldmin = std::max<int64_t>(1, n);
+  if (lda < ldmin) return -6;
+  if (ldb < ldmin) return -7;
+  const bool wantQ = o.qmode != HT_QZ_NONE, wantZ = o.zmode != HT_QZ_NONE;
+  if (wantQ && ldq < ldmin) return -8;
+  if (wantZ && ldz < ldmin) return -9;
+  if (n > 0 && (!A || !B)) return !A ? -1 : -2;
+  if (n > 0 && wantQ && !Q) return -3;
+  if (n > 0 && wantZ && !Z) return -4;
+  if (o.prec != HT_PREC_FP64) return HT_ERR_UNSUPPORTED;
+  if (o.qmode == HT_QZ_ACCUMULATE || o.zmode == HT_QZ_ACCUMULATE) return HT_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n == 0) return 0;
+
+  const int ni = (int)n;
+  if (wantQ) set_identity(st, Q, ni, (int)ldq);
+  if (wantZ) set_identity(st, Z, ni, (int)ldz);
+
+  if (o.flags & HT_FLAG_CHECK_FINITE) {
+    int* bad = nullptr;
+    if (hipMalloc(&bad, sizeof(int)) != hipSuccess) return HT_ERR_HIP;
+    (void)hipMemsetAsync(bad, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_check_finite, dim3((ni + 255) / 256, ni), dim3(256), 0, st, ni, ni, A,
+                       (int)lda, bad);
+    hipLaunchKernelGGL(k_check_finite, dim3((ni + 255) / 256, ni), dim3(256), 0, st, ni, ni, B,
+                       (int)ldb, bad);
+    int hbad = 0;
+    (void)hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    if (hbad) return HT_ERR_NONFINITE;
+  }
+
+  Work w;
+  const size_t need = layout(&w, ni, o.nb, nullptr) + 256;
+  char* base = (char*)workspace;
+  bool owned = false;
+  if (workspace) {
+    if (ws_bytes < need || ((uintptr_t)workspace & 255)) return HT_ERR_WORKSPACE;
+  } else {
+    if (hipMalloc((void**)&base, need) != hipSuccess) return HT_ERR_HIP;
+    owned = true;
+  }
+  layout(&w, ni, o.nb, base);
+  (void)hipMemsetAsync(w.flags, 0, ((ni + 63) / 64 + 2) * sizeof(int), st);
+
+  static int* pinned = nullptr;
+  if (!pinned) {
+    if (hipHostMalloc((void**)&pinned, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      if (owned) (void)hipFree(base);
+      return HT_ERR_HIP;
+    }
+  }
+  Ctx c;
+  c.st = st;
+  c.w = &w;
+  c.n = ni;
+  c.nb = o.nb;
+  c.A = A; c.B = B; c.Q = Q; c.Z = Z;
+  c.lda = (int)lda; c.ldb = (int)ldb; c.ldq = (int)ldq; c.ldz = (int)ldz;
+  c.wantQ = wantQ;
+  c.wantZ = wantZ;
+  c.opt = o;
+  c.host_ints = pinned;
+  rc = run(c);
+  const hipError_t le = hipGetLastError();
+  if (rc == 0 && le != hipSuccess) { g_last_hip = le; rc = HT_ERR_HIP; }
+  if (stats || owned) (void)hipStreamSynchronize(st);
+  if (stats) {
+    (void)hipMemcpy(pinned, w.ints, 8 * sizeof(int), hipMemcpyDeviceToHost);
+    stats->columns = c.columns;
+    stats->cols_extra_ir = c.cols_extra_ir;
+    stats->ir_steps = c.ir_steps;
+    stats->ir_failures = c.ir_failures;
+    stats->absorptions = c.absorptions;
+    stats->scaled_solves = pinned[5];
+    stats->flops = c.flops;
+    stats->ms_total = std::chrono::duration<double, std::milli>(
+        std::chrono::steady_clock::now() - t0).count();
+  }
+  if (owned) (void)hipFree(base);
+  return rc;
+}
+
+const char* ht_strerror(int code) {
+  if (code < 0) return "invalid argument";
+  switch (code) {
+    case HT_OK: return "success";
+    case HT_ERR_HIP: return "HIP runtime error";
+    case HT_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case HT_ERR_NONFINITE: return "NaN or Inf in the input";
+    case HT_ERR_UNSUPPORTED: return "unsupported option combination";
+    case HT_ERR_NOLIB: return "device code missing for this GPU";
+  }
+  return "unknown error";
+}
+
+const char* ht_version(void) { return "htred 0.1 gfx950"; }
+
+size_t ht_batched_workspace_size(int32_t batch, int32_t nmax, const ht_options* opt) {
+  (void)batch; (void)nmax; (void)opt;
+  return 0;
+}
+
+int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
+                      double* const* B_dev, double* const* Q_dev, double* const* Z_dev,
+                      const int32_t* ld_dev, int32_t* info_dev, int32_t nmax,
+                      const ht_options* opt, void* workspace, size_t ws_bytes, void* stream) {
+  (void)batch; (void)n_dev; (void)A_dev; (void)B_dev; (void)Q_dev; (void)Z_dev; (void)ld_dev;
+  (void)info_dev; (void)nmax; (void)opt; (void)workspace; (void)ws_bytes; (void)stream;
+  return HT_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

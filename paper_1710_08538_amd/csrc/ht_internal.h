@@ -1,0 +1,100 @@
+// ht_internal.h -- internal declarations shared by the HIP translation units
+// of libhtred.so (kernel launchers and device helpers).  Not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace htk {
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.  All matrices are column-major FP64; every launcher
+// enqueues on `st` and never synchronises.
+// ---------------------------------------------------------------------------
+
+// C(m x n) = alpha * op(A) * op(B) + beta * C, op(X) = X or X^T.
+// k is the contraction length.  beta == 0 ignores C's contents.
+void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k,
+          double alpha, const double* A, int lda, const double* B, int ldb,
+          double beta, double* C, int ldc);
+
+// y(0:m) = alpha * X(0:m, 0:k) * x + beta * y; x has stride incx.
+// `partials` must hold ceil(k/1024)*m doubles when k > 1024.
+void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
+            const double* x, int incx, double beta, double* y, double* partials);
+
+// z(0:k) = alpha * X(0:m, 0:k)^T * x + beta * z.  `partials` >= k * 16 doubles.
+void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
+            const double* x, double beta, double* z, double* partials);
+
+// y = B * x for upper triangular B (m x m); y and x distinct.
+void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x,
+                double* y, double* partials);
+
+// Overflow-safe upper triangular solve B x = 2^{-E} c, E >= 0 returned in
+// *E_dev (device int); x distinct from c.  `flags` holds ceil(m/64) ints,
+// `exps` the same; epoch must differ from every earlier call's on `flags`.
+void trsv_upper_scaled(hipStream_t st, int m, const double* B, int ldb,
+                       const double* c, double* x, int* exps, int* flags,
+                       int epoch, int* E_dev);
+
+// Householder reflector (LAPACK convention): for x of length m at `x`,
+// v (written to `v`, v[0] = 1) and tau with (I - tau v v^T) x = beta e1,
+// beta = -sign(x0) ||x||.  Writes tau to *tau and beta to *beta.  If
+// `overwrite`, x is replaced by (beta, 0, ..., 0).
+void house(hipStream_t st, int m, double* x, double* v, double* tau, double* beta,
+           bool overwrite);
+
+// Small-matrix kernels on one workgroup (k <= 128).
+// Appends a reflector to a compact-WY factor: T(0:kk, kk) = -tau T(0:kk,0:kk) z,
+// T(kk, kk) = tau, with z (kk) on device.
+void wy_append(hipStream_t st, double* T, int ldt, int kk, const double* z,
+               const double* tau);
+// y(0:k) = op(T) x for upper triangular T (k x k), scaled by alpha.
+void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt,
+                const double* x, double alpha, double* y);
+
+// Elementwise helpers.
+void fill(hipStream_t st, double* x, int m, double v);
+void copy(hipStream_t st, double* dst, const double* src, int m);
+void copy_mat(hipStream_t st, int m, int n, const double* src, int lds, double* dst, int ldd);
+void set_identity(hipStream_t st, double* X, int n, int ld);
+void zero_lower(hipStream_t st, double* X, int n, int ld, int offset);
+void zero_mat(hipStream_t st, double* X, int m, int n, int ld);
+// x *= 2^e (e from device int; e may be negative).
+void scale_pow2(hipStream_t st, double* x, int m, const int* e_dev, int sign);
+
+// Frobenius norm of an m x n matrix into *out (device), two-pass deterministic.
+void fro_norm(hipStream_t st, int m, int n, const double* X, int ld, double* out,
+              double* partials);
+
+// Replace exactly zero or subnormal diagonal entries of the trailing block
+// B(s:n, s:n) by 2 u rho normB (rho from the counter-based normal stream).
+void fix_diagonal(hipStream_t st, double* B, int ldb, int s, int n,
+                  const double* normB, uint64_t seed, uint64_t salt, int* count_dev);
+
+// Panel-step helpers (single workgroup unless noted).
+// IR residual verdict: r = 2^{-Erhs} c - w (c = e0 if c==NULL), returns status.
+void ir_residual(hipStream_t st, int m, const double* w, const double* c,
+                 const int* Erhs, double* r, const double* x, const double* normB,
+                 double tol_factor, int* status, double* norms);
+
+// x = 2^{-E2} x + d (IR update), Erhs += E2.
+void ir_update(hipStream_t st, int m, double* x, const double* d, const int* E2,
+               int* Erhs);
+
+// Chain factorisation of a w x k tile (w <= 2*KMAX) held in global memory.
+// mode 0: QR (tile = Qf [R; 0]), mode 1: QL (tile = Qf [0; L]).
+// On exit the tile holds R (resp. L) with exact zeros elsewhere, and
+// Qf = I - V W^T with V, W (w x k, ld w) written to Vout, Wout.
+void chain_factor(hipStream_t st, int mode, int w, int k, double* tile, int ldt,
+                  double* Vout, double* Wout, double* Tscratch);
+
+// Same as chain_factor but the tile is given transposed: the kernel factors
+// X = tile^T (w x k), tile is k x w with leading dimension ldt, and the
+// result factor is written back transposed.
+void chain_factor_t(hipStream_t st, int mode, int w, int k, double* tile, int ldt,
+                    double* Vout, double* Wout, double* Tscratch);
+
+int num_cus();
+
+}  // namespace htk

@@ -1,0 +1,314 @@
+// ht_panel.hip -- kernels of the panel reduction (Sec. 3.2): reflector
+// generation, the overflow-safe triangular solve behind the opposite
+// reflectors, iterative-refinement bookkeeping, compact-WY factor updates.
+#include "ht_device.h"
+#include "ht_internal.h"
+
+namespace htk {
+
+static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Householder reflector of a device vector (one 1024-thread workgroup).
+// Reflector of Sec. 2.1 in the LAPACK sign convention: H x = beta e1 with
+// beta = -sign(x0) ||x||_2; the norm is accumulated on x / max|x| so that
+// entries near the FP64 range limits neither overflow nor underflow.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_house(int m, double* x, double* v, double* tau_out,
+                                                double* beta_out, int overwrite) {
+  __shared__ double sh[16];
+  double amax = 0.0;
+  for (int i = 1 + threadIdx.x; i < m; i += 1024) amax = fmax(amax, fabs(x[i]));
+  amax = block_max(amax, sh);
+  double ss = 0.0;
+  if (amax > 0.0) {
+    const double inv = 1.0 / amax;
+    for (int i = 1 + threadIdx.x; i < m; i += 1024) {
+      double t = x[i] * inv;
+      ss = fma(t, t, ss);
+    }
+  }
+  ss = block_sum(ss, sh);
+  const double alpha = x[0];
+  const double xnorm = amax * sqrt(ss);
+  const Refl r = make_refl(alpha, xnorm);
+  for (int i = 1 + threadIdx.x; i < m; i += 1024) {
+    double xi = x[i];
+    v[i] = xi * r.scal;
+    if (overwrite) x[i] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    v[0] = 1.0;
+    if (overwrite) x[0] = r.beta;
+    tau_out[0] = r.tau;
+    beta_out[0] = r.beta;
+  }
+}
+
+void house(hipStream_t st, int m, double* x, double* v, double* tau, double* beta,
+           bool overwrite) {
+  hipLaunchKernelGGL(k_house, dim3(1), dim3(1024), 0, st, m, x, v, tau, beta,
+                     overwrite ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Compact-WY append (Sec. 2.4, used for S in step b and T in step d):
+// T(0:kk, kk) = -tau T(0:kk, 0:kk) z,  T(kk, kk) = tau.
+// ---------------------------------------------------------------------------
+__global__ void k_wy_append(double* T, int ldt, int kk, const double* z, const double* tau) {
+  __shared__ double zs[128];
+  const int t = threadIdx.x;
+  if (t < kk) zs[t] = z[t];
+  __syncthreads();
+  const double ta = tau[0];
+  if (t < kk) {
+    double s = 0.0;
+    for (int c = t; c < kk; ++c) s = fma(T[t + (size_t)c * ldt], zs[c], s);
+    T[t + (size_t)kk * ldt] = -ta * s;
+  }
+  if (t == 0) T[kk + (size_t)kk * ldt] = ta;
+}
+void wy_append(hipStream_t st, double* T, int ldt, int kk, const double* z, const double* tau) {
+  hipLaunchKernelGGL(k_wy_append, dim3(1), dim3(128), 0, st, T, ldt, kk, z, tau);
+}
+
+// y = alpha op(T) x, T upper triangular k x k (k <= 128)
+__global__ void k_trmv_small(int trans, int k, const double* T, int ldt, const double* x,
+                             double alpha, double* y) {
+  __shared__ double xs[128];
+  const int t = threadIdx.x;
+  if (t < k) xs[t] = x[t];
+  __syncthreads();
+  if (t >= k) return;
+  double s = 0.0;
+  if (!trans) {
+    for (int c = t; c < k; ++c) s = fma(T[t + (size_t)c * ldt], xs[c], s);
+  } else {
+    for (int c = 0; c <= t; ++c) s = fma(T[c + (size_t)t * ldt], xs[c], s);
+  }
+  y[t] = alpha * s;
+}
+void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt, const double* x,
+                double alpha, double* y) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_trmv_small, dim3(1), dim3(128), 0, st, trans ? 1 : 0, k, T, ldt, x,
+                     alpha, y);
+}
+
+// ---------------------------------------------------------------------------
+// Overflow-safe upper triangular solve B x = 2^{-E} c.
+//
+// Rows are split into 64-row blocks; block i is solved by one workgroup after
+// the blocks below it have been published (per-block ready flags, no grid
+// barrier).  Each published block carries its own power-of-two exponent e_i
+// (true value = x_i 2^{e_i}), so the solution may span far more than the
+// FP64 range: back substitution with a triangular matrix whose diagonal is
+// small grows geometrically.  Inside a block the substitution runs on one
+// wavefront and rescales by 2^-600 whenever the next entry would exceed
+// 2^600 times its pivot.  A final pass brings all blocks to the largest
+// exponent E (entries smaller by more than the FP64 range become zero) and
+// reports E: only the direction of x enters an opposite reflector (Lemma 2.1).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_trsv(int m, const double* __restrict__ B, int ldb,
+                                              const double* __restrict__ c, double* x, int* exps,
+                                              int* flags, int epoch) {
+  const int nb = (m + 63) >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double red[4][64];
+  for (int ib = nb - 1 - (int)blockIdx.x; ib >= 0; ib -= (int)gridDim.x) {
+    const int r0 = ib << 6;
+    const int nr = min(64, m - r0);
+    const int row = r0 + lane;
+    const bool live = lane < nr;
+    double acc = 0.0;
+    int E = 0;
+    for (int cb = nb - 1; cb > ib; --cb) {
+      if (threadIdx.x == 0) {
+        while (__hip_atomic_load(&flags[cb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch)
+          __builtin_amdgcn_s_sleep(1);
+      }
+      __syncthreads();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int ec = __hip_atomic_load(&exps[cb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ec > E) { acc = ldexp(acc, E - ec); E = ec; }
+      const double f = ldexp(1.0, ec - E);
+      const int cbase = (cb << 6) + wave * 16;
+      if (live) {
+        const double* p = B + (size_t)row;
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+          const int col = cbase + q;
+          if (col < m) {
+            const double xv = __hip_atomic_load(&x[col], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc = fma(p[(size_t)col * ldb], xv * f, acc);
+          }
+        }
+      }
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+      const double tot = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+      double rhs = live ? (ldexp(c[row], -E) - tot) : 0.0;
+      double Brow[64];
+#pragma unroll
+      for (int q = 0; q < 64; ++q)
+        Brow[q] = (live && q < nr && q > lane) ? B[(size_t)row + (size_t)(r0 + q) * ldb] : 0.0;
+      const double d_own = live ? B[(size_t)row + (size_t)row * ldb] : 1.0;
+      // A zero pivot survives only when ||B||_F = 0 (fix_diagonal replaces
+      // the others); then every direction solves B x = 0 and we take d = 1.
+      const double dinv = (d_own != 0.0) ? 1.0 / d_own : 1.0;
+      int e = E;
+      double xo = 0.0;
+#pragma unroll
+      for (int r = 63; r >= 0; --r) {
+        if (r < nr) {
+          double t = readlane_d(rhs, r);
+          const double dr0 = readlane_d(d_own, r);
+          const double dr = (dr0 != 0.0) ? dr0 : 1.0;
+          int guard = 0;
+          while (!(fabs(t) <= kBig * fabs(dr)) && guard < 8) {
+            rhs *= kShrink;
+            xo *= kShrink;
+            e += kShrinkExp;
+            t = readlane_d(rhs, r);
+            ++guard;
+          }
+          const double xr = t * readlane_d(dinv, r);
+          if (lane == r) xo = xr;
+          rhs = fma(-Brow[r], xr, rhs);
+        }
+      }
+      if (live) __hip_atomic_store(&x[row], xo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) __hip_atomic_store(&exps[ib], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) __hip_atomic_store(&flags[ib], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+// Normalise blocks to the largest exponent; E_dev = max exponent.
+__global__ __launch_bounds__(1024) void k_trsv_fin(int m, double* x, const int* exps, int* E_dev) {
+  __shared__ int smax[16];
+  const int nb = (m + 63) >> 6;
+  int e = 0;
+  for (int i = threadIdx.x; i < nb; i += 1024) e = max(e, exps[i]);
+  e = wave_max_i(e);
+  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = e;
+  __syncthreads();
+  int E = 0;
+  for (int i = 0; i < 16; ++i) E = max(E, smax[i]);
+  for (int i = threadIdx.x; i < m; i += 1024) {
+    const int d = exps[i >> 6] - E;
+    if (d != 0) x[i] = ldexp(x[i], d);
+  }
+  if (threadIdx.x == 0) E_dev[0] = E;
+}
+
+static int trsv_grid_cap() {
+  static int cap = 0;
+  if (cap == 0) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trsv, 256, 0) != hipSuccess || per < 1)
+      per = 1;
+    cap = per * num_cus();
+  }
+  return cap;
+}
+
+void trsv_upper_scaled(hipStream_t st, int m, const double* B, int ldb, const double* c,
+                       double* x, int* exps, int* flags, int epoch, int* E_dev) {
+  if (m <= 0) return;
+  const int nb = (m + 63) / 64;
+  const int grid = std::min(nb, trsv_grid_cap());
+  void* args[] = {(void*)&m, (void*)&B, (void*)&ldb, (void*)&c, (void*)&x,
+                  (void*)&exps, (void*)&flags, (void*)&epoch};
+  (void)hipLaunchCooperativeKernel((const void*)k_trsv, dim3(grid), dim3(256), args, 0, st);
+  hipLaunchKernelGGL(k_trsv_fin, dim3(1), dim3(1024), 0, st, m, x, exps, E_dev);
+}
+
+// ---------------------------------------------------------------------------
+// Iterative refinement (Sec. 2.3, step c of Sec. 3.2.2).
+// r = 2^{-Erhs} c - w (c = e1 when c == NULL); status = 1 when
+// ||r||_2 <= tol_factor * u * ||B||_F * ||x||_2.  norms[0..1] = ||r||, ||x||.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_ir_residual(int m, const double* w, const double* c,
+                                                      const int* Erhs, double* r, const double* x,
+                                                      const double* normB, double tol_factor,
+                                                      int* status, double* norms) {
+  __shared__ double sh[16];
+  const int E = Erhs[0];
+  double rmax = 0.0, xmax = 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) {
+    double ci = c ? c[i] : (i == 0 ? 1.0 : 0.0);
+    double ri = ldexp(ci, -E) - w[i];
+    r[i] = ri;
+    rmax = fmax(rmax, fabs(ri));
+    xmax = fmax(xmax, fabs(x[i]));
+  }
+  rmax = block_max(rmax, sh);
+  xmax = block_max(xmax, sh);
+  double rs = 0.0, xs = 0.0;
+  const double ir = rmax > 0.0 ? 1.0 / rmax : 0.0, ix = xmax > 0.0 ? 1.0 / xmax : 0.0;
+  for (int i = threadIdx.x; i < m; i += 1024) {
+    double a = r[i] * ir, b = x[i] * ix;
+    rs = fma(a, a, rs);
+    xs = fma(b, b, xs);
+  }
+  rs = block_sum(rs, sh);
+  xs = block_sum(xs, sh);
+  if (threadIdx.x == 0) {
+    const double rn = rmax * sqrt(rs), xn = xmax * sqrt(xs);
+    norms[0] = rn;
+    norms[1] = xn;
+    const double tol = tol_factor * kUnitRoundoff * normB[0];
+    status[0] = (rn <= tol * xn) ? 1 : 0;
+  }
+}
+void ir_residual(hipStream_t st, int m, const double* w, const double* c, const int* Erhs,
+                 double* r, const double* x, const double* normB, double tol_factor, int* status,
+                 double* norms) {
+  hipLaunchKernelGGL(k_ir_residual, dim3(1), dim3(1024), 0, st, m, w, c, Erhs, r, x, normB,
+                     tol_factor, status, norms);
+}
+
+__global__ void k_ir_update(int m, double* x, const double* d, const int* E2, int* Erhs,
+                            int last_block) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = E2[0];
+  if (i < m) x[i] = ldexp(x[i], -e) + d[i];
+  if (last_block && i == 0) Erhs[0] += e;
+}
+void ir_update(hipStream_t st, int m, double* x, const double* d, const int* E2, int* Erhs) {
+  // the exponent is bumped by a separate one-thread launch after all blocks
+  // have read E2 (E2 and Erhs may be distinct words; order kept by the stream)
+  hipLaunchKernelGGL(k_ir_update, dim3(cdiv(m, 256)), dim3(256), 0, st, m, x, d, E2, Erhs, 0);
+  hipLaunchKernelGGL(k_ir_update, dim3(1), dim3(1), 0, st, 0, x, d, E2, Erhs, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Zero-diagonal rule (Sec. 3.2.1, Remark 2.2): a zero (or subnormal) diagonal
+// entry of B(s:n, s:n) becomes 2 u rho ||B||_F with rho ~ N(0,1).
+// ---------------------------------------------------------------------------
+__global__ void k_fix_diag(double* B, int ldb, int s, int n, const double* normB, uint64_t seed,
+                           uint64_t salt, int* count) {
+  const int i = s + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* p = B + (size_t)i + (size_t)i * ldb;
+  const double d = *p;
+  if (normB[0] > 0.0 && fabs(d) < 2.2250738585072014e-308) {
+    double rho = normal_draw(seed, salt * (uint64_t)n + (uint64_t)i);
+    if (rho == 0.0) rho = 1.0;
+    *p = 2.0 * kUnitRoundoff * rho * normB[0];
+    atomicAdd(count, 1);
+  }
+}
+void fix_diagonal(hipStream_t st, double* B, int ldb, int s, int n, const double* normB,
+                  uint64_t seed, uint64_t salt, int* count_dev) {
+  if (n - s <= 0) return;
+  hipLaunchKernelGGL(k_fix_diag, dim3(cdiv(n - s, 256)), dim3(256), 0, st, B, ldb, s, n, normB,
+                     seed, salt, count_dev);
+}
+
+}  // namespace htk

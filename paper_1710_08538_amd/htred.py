@@ -1,0 +1,154 @@
+"""Thin ctypes binding of libhtred.so (C ABI declared in include/htred.h).
+
+Argument marshalling only: every step of the reduction runs in the HIP
+library.  Matrices are torch FP64 CUDA(HIP) tensors in column-major layout
+(stride(0) == 1), e.g. ``torch.from_numpy(np.asfortranarray(M)).cuda()``
+or ``colmajor_empty(n)``.  The library must be built (``build.py``); if it
+is missing or cannot be loaded every call raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libhtred.so")
+
+HT_QZ_IDENTITY, HT_QZ_ACCUMULATE, HT_QZ_NONE = 0, 1, 2
+HT_PREC_FP64, HT_PREC_SPLIT_BF16, HT_PREC_SPLIT_FP8 = 0, 1, 2
+HT_FLAG_CHECK_FINITE = 1
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("max_ir", ctypes.c_int32), ("qmode", ctypes.c_int32),
+                ("zmode", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("n_slices", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("ir_tol_factor", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("columns", ctypes.c_int64), ("cols_extra_ir", ctypes.c_int64),
+                ("ir_steps", ctypes.c_int64), ("ir_failures", ctypes.c_int64),
+                ("absorptions", ctypes.c_int64), ("scaled_solves", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class HTError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libhtred.so (after torch has initialised its HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HTError("libhtred.so not built: run `python -m paper_1710_08538_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+        L.ht_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.ht_default_options.restype = ctypes.c_int
+        L.ht_workspace_size.argtypes = [i64, ctypes.POINTER(Options)]
+        L.ht_workspace_size.restype = ctypes.c_size_t
+        L.ht_reduce.argtypes = [vp, vp, vp, vp, i64, i64, i64, i64, i64,
+                                ctypes.POINTER(Options), ctypes.POINTER(Stats), vp,
+                                ctypes.c_size_t, vp]
+        L.ht_reduce.restype = ctypes.c_int
+        L.ht_batched_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.POINTER(Options)]
+        L.ht_batched_workspace_size.restype = ctypes.c_size_t
+        L.ht_reduce_batched.argtypes = [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                        ctypes.c_int32, ctypes.POINTER(Options), vp,
+                                        ctypes.c_size_t, vp]
+        L.ht_reduce_batched.restype = ctypes.c_int
+        L.ht_strerror.argtypes = [ctypes.c_int]
+        L.ht_strerror.restype = ctypes.c_char_p
+        L.ht_version.argtypes = []
+        L.ht_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def options(**kw):
+    o = Options()
+    lib().ht_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, v)
+    return o
+
+
+def colmajor_empty(n, m=None, device="cuda"):
+    """Uninitialised n x m FP64 tensor with column-major strides (1, n)."""
+    m = n if m is None else m
+    return torch.empty((m, n), dtype=torch.float64, device=device).t()
+
+
+def to_device_colmajor(M, device="cuda"):
+    """Copy a numpy/torch matrix to a column-major FP64 device tensor."""
+    t = torch.as_tensor(M, dtype=torch.float64)
+    out = colmajor_empty(t.shape[0], t.shape[1], device=device)
+    out.copy_(t)
+    return out
+
+
+def _ld(t, n, name):
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("%s must be a float64 GPU tensor" % name)
+    if tuple(t.shape) != (n, n):
+        raise ValueError("%s must be %dx%d" % (name, n, n))
+    if n > 0 and t.stride(0) != 1:
+        raise ValueError("%s must be column-major (stride(0) == 1)" % name)
+    return max(t.stride(1), max(n, 1))
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().ht_strerror(rc).decode()
+        raise HTError("ht_reduce failed: %d (%s)" % (rc, msg))
+
+
+def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
+           prec=HT_PREC_FP64, stats=False, workspace=None, stream=None, check_finite=False):
+    """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
+
+    A, B: n x n column-major float64 GPU tensors (B upper triangular).
+    Q, Z: optional preallocated outputs (allocated when None).
+    workspace: optional uint8 GPU tensor of >= workspace_size(n) bytes.
+    """
+    n = A.shape[0]
+    lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
+    if Q is None:
+        Q = colmajor_empty(n, device=A.device)
+    if Z is None:
+        Z = colmajor_empty(n, device=A.device)
+    ldq, ldz = _ld(Q, n, "Q"), _ld(Z, n, "Z")
+    o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
+                flags=HT_FLAG_CHECK_FINITE if check_finite else 0)
+    st = Stats()
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    rc = lib().ht_reduce(A.data_ptr(), B.data_ptr(), Q.data_ptr(), Z.data_ptr(), n, lda, ldb,
+                         ldq, ldz, ctypes.byref(o), ctypes.byref(st) if stats else None,
+                         ws_ptr, ws_bytes, s.cuda_stream)
+    _check(rc)
+    if stats:
+        return Q, Z, st.as_dict()
+    return Q, Z
+
+
+def workspace_size(n, nb=64):
+    return lib().ht_workspace_size(n, ctypes.byref(options(nb=nb)))
+
+
+def version():
+    return lib().ht_version().decode()
