@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Benchmark: HouseHT reduction of one n x n pencil on one MI355X.
+
+One step = one full HT reduction (Algorithm 1: panels + absorption) of the
+synthetic pencil, restored from a pristine device copy at the start of the
+step (a device-to-device copy of A and B, < 0.1% of the step).  The default
+workload is the n = 16384 FP64 pencil with an ill-conditioned triangular B
+(panel width nb = 128).  Prints ONE JSON line.
+
+value = nominal GFLOP/s = 39 n^3 / time (the nominal count of the basic
+two-block absorption scheme); the executed flop count, time per step,
+backward errors and the IR statistics are reported beside it.
+
+roofline: the kernel class with the largest device time in the timed steps,
+timed by the library with HIP events on its own stream; achieved =
+algorithmic work of that class / its summed launch durations.
+
+cpu_baseline: the CPU oracle (Moler-Stewart, plain C, one thread) on the
+first columns of the same pencil, extrapolated to the whole reduction by its
+per-column rotation count.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HT reduction GFLOP/s + time at n=16384 FP64 (vs split-prec/batched), backward err"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def nominal_flops(n):
+    return 39.0 * float(n) ** 3
+
+
+def cpu_baseline(A0, B0, target_s):
+    """Time the Moler-Stewart oracle on a bounded prefix of the reduction."""
+    import oracle
+    n = A0.shape[0]
+    total_rot = (n - 2) * (n - 1) / 2.0
+    c = 1
+    t = time.time()
+    oracle.ms_ht(A0, B0, ncols=c)
+    dt = time.time() - t
+    # grow the prefix while the estimated time stays under the target
+    per_col = dt
+    if n < 8192 and per_col * 2 < target_s:
+        c = max(1, min(n - 2, int(target_s / max(per_col, 1e-3))))
+        t = time.time()
+        oracle.ms_ht(A0, B0, ncols=c)
+        dt = time.time() - t
+    sample_rot = sum(n - j - 2 for j in range(c))
+    t_full = dt * total_rot / sample_rot
+    return {"value": nominal_flops(n) / t_full / 1e9, "unit": "GFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": ("Moler-Stewart Givens HT reduction (plain C, 1 thread) on the first %d of "
+                       "%d columns of the same pencil in %.1f s; full time %.0f s extrapolated by "
+                       "rotations per column" % (c, n - 2, dt, t_full)),
+            "time_s_extrapolated": t_full}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="n16384")
+    ap.add_argument("--n", type=int, default=None, help="override the order (same generator)")
+    ap.add_argument("--nb", type=int, default=128)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "bf16", "fp8"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the single-pencil reduction is not "
+              "sharded across GPUs); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1710_08538_amd import htred, inputs
+    from oracle import checks
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = {"fp64": htred.HT_PREC_FP64, "bf16": htred.HT_PREC_SPLIT_BF16,
+            "fp8": htred.HT_PREC_SPLIT_FP8}[args.prec]
+    A0, B0 = inputs.workload(args.workload, n=args.n)
+    n = A0.shape[0]
+    print("bench: workload %s n=%d nb=%d prec=%s" % (args.workload, n, args.nb, args.prec),
+          file=sys.stderr, flush=True)
+    A0d = htred.to_device_colmajor(A0)
+    B0d = htred.to_device_colmajor(B0)
+    A = htred.colmajor_empty(n)
+    B = htred.colmajor_empty(n)
+    Q = htred.colmajor_empty(n)
+    Z = htred.colmajor_empty(n)
+    ws = torch.empty(htred.workspace_size(n, nb=args.nb), dtype=torch.uint8, device="cuda")
+
+    def step(profile):
+        A.copy_(A0d)
+        B.copy_(B0d)
+        return htred.reduce(A, B, Q, Z, nb=args.nb, prec=prec, stats=True, workspace=ws,
+                            profile=profile)[2]
+
+    for i in range(args.warmup):
+        t = time.time()
+        step(False)
+        torch.cuda.synchronize()
+        print("bench: warmup %d done in %.2f s" % (i, time.time() - t), file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.time()
+    stats = []
+    for i in range(args.steps):
+        stats.append(step(True))
+        print("bench: step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    # roofline of the dominant kernel class over the timed steps
+    ncls = len(htred.PROF_CLASSES)
+    prof_ms = [sum(s["prof_ms"][c] for s in stats) for c in range(ncls)]
+    prof_work = [sum(s["prof_work"][c] for s in stats) for c in range(ncls)]
+    prof_l = [sum(s["prof_launches"][c] for s in stats) for c in range(ncls)]
+    dom = max(range(ncls), key=lambda c: prof_ms[c])
+    if htred.PROF_CLASSES[dom] in ("wy", "chain"):
+        achieved = prof_work[dom] / (prof_ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+    else:
+        achieved = prof_work[dom] / (prof_ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof["kernel_class"] = htred.PROF_CLASSES[dom]
+    roof["launches_per_step"] = prof_l[dom] / args.steps
+    breakdown = {htred.PROF_CLASSES[c]: {"ms_per_step": prof_ms[c] / args.steps,
+                                         "launches_per_step": prof_l[c] / args.steps}
+                 for c in range(ncls)}
+
+    result = {
+        "metric": METRIC,
+        "value": nominal_flops(n) / (ms_per_step * 1e-3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == htred.HT_PREC_FP64 else ("f64-split-" + args.prec),
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "nb": args.nb,
+                   "generator": inputs.WORKLOADS[args.workload][0],
+                   "flop_model": "39 n^3 nominal"},
+        "time_s": ms_per_step / 1000.0,
+        "gflops_executed": stats[-1]["flops"] / (ms_per_step * 1e-3) / 1e9,
+        "ir": {k: stats[-1][k] for k in ("cols_extra_ir", "ir_steps", "ir_failures",
+                                         "absorptions", "scaled_solves")},
+        "kernel_ms_per_step": breakdown,
+        "roofline": roof,
+    }
+    if not args.no_check:
+        inv = checks.invariants(A0d, B0d, A, B, Q, Z)
+        result["backward_error"] = {k: inv[k] for k in ("bwd_A", "bwd_B", "orth_Q", "orth_Z",
+                                                       "zeros_H", "zeros_T")}
+        result["invariants_ok"] = bool(checks.invariants_ok(inv, n))
+    del A0d, B0d, A, B, Q, Z, ws
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        print("bench: cpu baseline ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(A0, B0, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

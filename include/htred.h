@@ -78,6 +78,17 @@ typedef struct {
 
 /* flags */
 #define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs) */
+#define HT_FLAG_PROFILE      2  /* time kernel classes with HIP events (stats) */
+
+/* Kernel classes reported in ht_stats.prof_* when HT_FLAG_PROFILE is set.
+ * prof_work is the algorithmic work of the class: flops for the
+ * contraction classes (WY, CHAIN), bytes for the streaming classes. */
+#define HT_PROF_WY     0  /* block-reflector updates of A, B, Q, Z (flops) */
+#define HT_PROF_TRSV   1  /* triangular solves with B (bytes of B read) */
+#define HT_PROF_TRMV   2  /* residual products with B (bytes of B read) */
+#define HT_PROF_YGEMV  3  /* Y = A V T columns (bytes of A read) */
+#define HT_PROF_CHAIN  4  /* QL/QR/RQ chain factorisations (flops) */
+#define HT_PROF_NCLASS 8
 
 typedef struct {
     int64_t columns;          /* columns reduced */
@@ -88,6 +99,9 @@ typedef struct {
     int64_t scaled_solves;    /* solves that needed overflow rescaling */
     double  flops;            /* flops executed, counted from launch shapes */
     double  ms_total;         /* wall time of the call (ms), host clock */
+    double  prof_ms[HT_PROF_NCLASS];       /* summed launch durations (HIP events) */
+    double  prof_work[HT_PROF_NCLASS];     /* algorithmic flops or bytes */
+    int64_t prof_launches[HT_PROF_NCLASS]; /* launches timed */
 } ht_stats;
 
 /* Fills *opt with the defaults listed above.  Returns 0. */

@@ -101,32 +101,70 @@ void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k, double 
 }
 
 // ---------------------------------------------------------------------------
-// GEMV y = alpha X x + beta y.  Column chunks of KC columns per workgroup
-// write partial sums; a second kernel adds them in chunk order.
+// GEMV y = alpha X x + beta y and TRMV y = B x (B upper triangular).
+// Small k: one thread per row, one launch.  Large k: 64-row x KC-column
+// blocks (each wave a quarter of the columns, lanes = consecutive rows, so a
+// wave reads 512 contiguous bytes per column); partial sums per column chunk
+// are added in chunk order by a second kernel (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int KC = 1024;
+constexpr int KC = 512;
+constexpr int kSmallK = 256;
 
-__global__ __launch_bounds__(256) void k_gemv_n_part(int m, int k, const double* __restrict__ X,
-                                                     int ldx, const double* __restrict__ x,
-                                                     int incx, double* __restrict__ part) {
-  __shared__ double xs[KC];
-  const int c0 = blockIdx.y * KC;
-  const int kc = min(KC, k - c0);
-  for (int t = threadIdx.x; t < kc; t += 256) xs[t] = x[(size_t)(c0 + t) * incx];
+__global__ __launch_bounds__(256) void k_gemv_n_small(int m, int k, double alpha,
+                                                      const double* __restrict__ X, int ldx,
+                                                      const double* __restrict__ x, int incx,
+                                                      double beta, double* y) {
+  __shared__ double xs[kSmallK];
+  for (int t = threadIdx.x; t < k; t += 256) xs[t] = x[(size_t)t * incx];
   __syncthreads();
   const int row = blockIdx.x * 256 + threadIdx.x;
   if (row >= m) return;
-  const double* p = X + (size_t)row + (size_t)c0 * ldx;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const double* p = X + row;
+  double s0 = 0.0, s1 = 0.0;
   int c = 0;
-  for (; c + 4 <= kc; c += 4) {
+  for (; c + 2 <= k; c += 2) {
     s0 = fma(p[(size_t)c * ldx], xs[c], s0);
     s1 = fma(p[(size_t)(c + 1) * ldx], xs[c + 1], s1);
-    s2 = fma(p[(size_t)(c + 2) * ldx], xs[c + 2], s2);
-    s3 = fma(p[(size_t)(c + 3) * ldx], xs[c + 3], s3);
   }
-  for (; c < kc; ++c) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
-  part[(size_t)blockIdx.y * m + row] = (s0 + s1) + (s2 + s3);
+  if (c < k) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+  const double s = s0 + s1;
+  y[row] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[row]);
+}
+
+template <bool TRI>
+__global__ __launch_bounds__(256) void k_gemv_part(int m, int k, const double* __restrict__ X,
+                                                   int ldx, const double* __restrict__ x, int incx,
+                                                   double* __restrict__ part) {
+  __shared__ double xs[KC];
+  __shared__ double red[4][64];
+  const int row0 = blockIdx.x * 64;
+  const int c0 = blockIdx.y * KC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = row0 + lane;
+  if (TRI && c0 + KC <= row0) {  // chunk entirely below the diagonal
+    if (wave == 0 && row < m) part[(size_t)blockIdx.y * m + row] = 0.0;
+    return;
+  }
+  const int kc = min(KC, k - c0);
+  for (int t = threadIdx.x; t < kc; t += 256) xs[t] = x[(size_t)(c0 + t) * incx];
+  __syncthreads();
+  constexpr int CW = KC / 4;
+  int cs = wave * CW, ce = min(kc, cs + CW);
+  if (TRI) cs = max(cs, row - c0);
+  double s0 = 0.0, s1 = 0.0;
+  if (row < m) {
+    const double* p = X + (size_t)row + (size_t)c0 * ldx;
+    int c = cs;
+    for (; c + 2 <= ce; c += 2) {
+      s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+      s1 = fma(p[(size_t)(c + 1) * ldx], xs[c + 1], s1);
+    }
+    if (c < ce) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+  }
+  red[wave][lane] = s0 + s1;
+  __syncthreads();
+  if (wave == 0 && row < m)
+    part[(size_t)blockIdx.y * m + row] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 __global__ __launch_bounds__(256) void k_gemv_n_fin(int m, int nch, const double* __restrict__ part,
@@ -141,26 +179,38 @@ __global__ __launch_bounds__(256) void k_gemv_n_fin(int m, int nch, const double
 void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
             const double* x, int incx, double beta, double* y, double* partials) {
   if (m <= 0) return;
-  if (k <= 0) {
-    hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, 0, partials,
-                       alpha, beta, y);
+  if (k <= kSmallK) {
+    hipLaunchKernelGGL(k_gemv_n_small, dim3(cdiv(m, 256)), dim3(256), 0, st, m, k, alpha, X, ldx,
+                       x, incx, beta, y);
     return;
   }
   const int nch = cdiv(k, KC);
-  hipLaunchKernelGGL(k_gemv_n_part, dim3(cdiv(m, 256), nch), dim3(256), 0, st, m, k, X, ldx, x,
-                     incx, partials);
+  hipLaunchKernelGGL(k_gemv_part<false>, dim3(cdiv(m, 64), nch), dim3(256), 0, st, m, k, X, ldx,
+                     x, incx, partials);
   hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nch, partials, alpha,
                      beta, y);
 }
 
+void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x, double* y,
+                double* partials) {
+  if (m <= 0) return;
+  const int nch = cdiv(m, KC);
+  hipLaunchKernelGGL(k_gemv_part<true>, dim3(cdiv(m, 64), nch), dim3(256), 0, st, m, m, B, ldb,
+                     x, 1, partials);
+  hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nch, partials, 1.0,
+                     0.0, y);
+}
+
 // ---------------------------------------------------------------------------
-// GEMV^T z = alpha X^T x + beta z: workgroup (column c, row chunk) partials.
+// GEMV^T z = alpha X^T x + beta z: workgroup (column c, row chunk); with one
+// chunk the result is written directly.
 // ---------------------------------------------------------------------------
 constexpr int RC = 4096;
 
 __global__ __launch_bounds__(256) void k_gemv_t_part(int m, int k, const double* __restrict__ X,
                                                      int ldx, const double* __restrict__ x,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, int direct,
+                                                     double alpha, double beta, double* z) {
   __shared__ double sh[4];
   const int c = blockIdx.x;
   const int r0 = blockIdx.y * RC;
@@ -169,7 +219,10 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(int m, int k, const double*
   double s = 0.0;
   for (int r = r0 + threadIdx.x; r < r1; r += 256) s = fma(p[r], x[r], s);
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[(size_t)blockIdx.y * k + c] = s;
+  if (threadIdx.x == 0) {
+    if (direct) z[c] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * z[c]);
+    else part[(size_t)blockIdx.y * k + c] = s;
+  }
 }
 
 __global__ void k_gemv_t_fin(int k, int nch, const double* __restrict__ part, double alpha,
@@ -185,52 +238,16 @@ void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
             const double* x, double beta, double* z, double* partials) {
   if (k <= 0) return;
   const int nch = m > 0 ? cdiv(m, RC) : 0;
-  if (nch > 0)
-    hipLaunchKernelGGL(k_gemv_t_part, dim3(k, nch), dim3(256), 0, st, m, k, X, ldx, x, partials);
-  hipLaunchKernelGGL(k_gemv_t_fin, dim3(cdiv(k, 128)), dim3(128), 0, st, k, nch, partials, alpha,
-                     beta, z);
-}
-
-// ---------------------------------------------------------------------------
-// TRMV y = B x, B upper triangular: like GEMV, chunks left of the row block
-// are skipped (they write zeros) and only entries with col >= row are read.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trmv_part(int m, const double* __restrict__ B, int ldb,
-                                                   const double* __restrict__ x,
-                                                   double* __restrict__ part) {
-  __shared__ double xs[KC];
-  const int c0 = blockIdx.y * KC;
-  const int kc = min(KC, m - c0);
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  const int rowblk_end = min(m, (int)(blockIdx.x * 256 + 256));
-  if (c0 + kc <= (int)(blockIdx.x * 256)) {  // chunk entirely below the diagonal
-    if (row < m) part[(size_t)blockIdx.y * m + row] = 0.0;
+  if (nch == 1) {
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(k, 1), dim3(256), 0, st, m, k, X, ldx, x, partials, 1,
+                       alpha, beta, z);
     return;
   }
-  (void)rowblk_end;
-  for (int t = threadIdx.x; t < kc; t += 256) xs[t] = x[c0 + t];
-  __syncthreads();
-  if (row >= m) return;
-  const double* p = B + (size_t)row + (size_t)c0 * ldb;
-  double s0 = 0.0, s1 = 0.0;
-  int cstart = max(0, row - c0);
-  int c = cstart;
-  for (; c + 2 <= kc; c += 2) {
-    s0 = fma(p[(size_t)c * ldb], xs[c], s0);
-    s1 = fma(p[(size_t)(c + 1) * ldb], xs[c + 1], s1);
-  }
-  for (; c < kc; ++c) s0 = fma(p[(size_t)c * ldb], xs[c], s0);
-  part[(size_t)blockIdx.y * m + row] = s0 + s1;
-}
-
-void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x, double* y,
-                double* partials) {
-  if (m <= 0) return;
-  const int nch = cdiv(m, KC);
-  hipLaunchKernelGGL(k_trmv_part, dim3(cdiv(m, 256), nch), dim3(256), 0, st, m, B, ldb, x,
-                     partials);
-  hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nch, partials, 1.0,
-                     0.0, y);
+  if (nch > 0)
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(k, nch), dim3(256), 0, st, m, k, X, ldx, x, partials,
+                       0, alpha, beta, z);
+  hipLaunchKernelGGL(k_gemv_t_fin, dim3(cdiv(k, 128)), dim3(128), 0, st, k, nch, partials, alpha,
+                     beta, z);
 }
 
 // ---------------------------------------------------------------------------

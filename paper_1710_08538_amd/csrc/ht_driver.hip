@@ -59,7 +59,7 @@ struct Work {
   double* pool[4][2];  // chain transform pools: [chain][V or W]
   double* Gws;
   double* dscal;       // [0] tau_u, [1] beta_u, [2] normB, [3..4] IR norms, [5] tau_v, [6] beta_v
-  int *flags, *exps, *ints;  // ints: [1] E_rhs, [2] E_corr, [3] status, [4] fixes, [5] scaled
+  int *flags, *ints;  // ints: [1] E_rhs, [2] E_corr, [3] status, [4] fixes, [5] scaled
   int epoch = 0;
 };
 
@@ -96,15 +96,13 @@ size_t layout(Work* w, int n, int nb, char* base) {
   w->Kt2 = take(N * K);
   w->P = take(N * 2 * K);
   w->Wk = take(N * K);
-  w->partials = take(std::max<size_t>(16 * N, 64 * K));
+  w->partials = take(std::max<size_t>(((N + 511) / 512 + 1) * N, 64 * K));
   const size_t poolsz = 2 * N * K + 4 * K * K;
   for (int c = 0; c < 4; ++c)
     for (int v = 0; v < 2; ++v) w->pool[c][v] = take(poolsz);
   w->Gws = take(2 * K * K + 8);
   w->dscal = take(64);
-  const size_t nblk = (N + 63) / 64 + 1;
-  w->flags = (int*)take((nblk + 1) / 2 + 1);
-  w->exps = (int*)take((nblk + 1) / 2 + 1);
+  w->flags = (int*)take(trsv_flag_bytes((int)N) / 8 + 1);
   w->ints = (int*)take(32);
   return off;
 }
@@ -135,6 +133,48 @@ __global__ void k_check_finite(int m, int n, const double* X, int ld, int* bad) 
 
 inline double* at(double* X, int ld, int r, int c) { return X + (size_t)r + (size_t)c * ld; }
 
+// Per-kernel-class device timing with HIP events (HT_FLAG_PROFILE).  Events
+// come from a pool kept for the life of the process.
+struct Prof {
+  bool on = false;
+  struct Rec { int cls; hipEvent_t a, b; double work; };
+  std::vector<Rec> recs;
+  size_t used = 0;
+  static std::vector<hipEvent_t>& pool() {
+    static std::vector<hipEvent_t> p;
+    return p;
+  }
+  hipEvent_t get() {
+    auto& p = pool();
+    if (used == p.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      p.push_back(e);
+    }
+    return p[used++];
+  }
+  int begin(hipStream_t st, int cls) {
+    if (!on) return -1;
+    Rec r{cls, get(), get(), 0.0};
+    (void)hipEventRecord(r.a, st);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(hipStream_t st, int idx, double work) {
+    if (idx < 0) return;
+    recs[idx].work = work;
+    (void)hipEventRecord(recs[idx].b, st);
+  }
+  void collect(ht_stats* s) {
+    for (auto& r : recs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) s->prof_ms[r.cls] += ms;
+      s->prof_work[r.cls] += r.work;
+      s->prof_launches[r.cls] += 1;
+    }
+  }
+};
+
 struct Ctx {
   hipStream_t st;
   Work* w;
@@ -144,6 +184,7 @@ struct Ctx {
   bool wantQ, wantZ;
   ht_options opt;
   int* host_ints;  // pinned mirror of w->ints
+  Prof prof;
   double flops = 0.0;
   int64_t cols_extra_ir = 0, ir_steps = 0, ir_failures = 0, absorptions = 0, columns = 0;
 };
@@ -152,8 +193,10 @@ struct Ctx {
 void right_apply(Ctx& c, double* X, int ld, int rows, int wdt, int k, const double* Vf,
                  const double* Wf) {
   if (rows <= 0 || wdt <= 0 || k <= 0) return;
+  const int pi = c.prof.begin(c.st, HT_PROF_WY);
   gemm(c.st, false, false, rows, k, wdt, 1.0, X, ld, Vf, wdt, 0.0, c.w->P, c.n);
   gemm(c.st, false, true, rows, wdt, k, -1.0, c.w->P, c.n, Wf, wdt, 1.0, X, ld);
+  c.prof.end(c.st, pi, 4.0 * rows * (double)wdt * k);
   c.flops += 4.0 * rows * (double)wdt * k;
 }
 
@@ -161,8 +204,10 @@ void right_apply(Ctx& c, double* X, int ld, int rows, int wdt, int k, const doub
 void left_apply(Ctx& c, double* X, int ld, int ncols, int wdt, int k, const double* Vf,
                 const double* Wf) {
   if (ncols <= 0 || wdt <= 0 || k <= 0) return;
+  const int pi = c.prof.begin(c.st, HT_PROF_WY);
   gemm(c.st, true, false, k, ncols, wdt, 1.0, Vf, wdt, X, ld, 0.0, c.w->P, k);
   gemm(c.st, false, false, wdt, ncols, k, -1.0, Wf, wdt, c.w->P, k, 1.0, X, ld);
+  c.prof.end(c.st, pi, 4.0 * ncols * (double)wdt * k);
   c.flops += 4.0 * ncols * (double)wdt * k;
 }
 
@@ -219,6 +264,17 @@ void sweep_cols_right(Ctx& c, double* X, int ld, int rows, int j, const Blocks& 
                 tV(*c.w, chain, wn.slot, bl.k), tW(*c.w, chain, wn.slot, bl.k));
 }
 
+// One chain factorisation, timed as HT_PROF_CHAIN (flops of a Householder
+// QR/QL of a wdt x k tile plus the T/W build: about 4 wdt k^2).
+void chain(Ctx& c, int mode, bool trans, int wdt, int k, double* tile, int ld, double* Vf,
+           double* Wf) {
+  const int pi = c.prof.begin(c.st, HT_PROF_CHAIN);
+  if (trans) chain_factor_t(c.st, mode, wdt, k, tile, ld, Vf, Wf, c.w->Gws);
+  else chain_factor(c.st, mode, wdt, k, tile, ld, Vf, Wf, c.w->Gws);
+  c.prof.end(c.st, pi, 4.0 * wdt * (double)k * k);
+  c.flops += 4.0 * wdt * (double)k * k;
+}
+
 int sync_status(Ctx& c) {
   (void)hipMemcpyAsync(c.host_ints, c.w->ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c.st);
   (void)hipStreamSynchronize(c.st);
@@ -236,7 +292,9 @@ void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, i
   trmv_small(c.st, false, nu, w.S, c.nb, w.tk, 1.0, w.tk2);
   gemv_n(c.st, L, nu, -1.0, w.U, n, w.tk2, 1, 1.0, ctil, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
-  trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.exps, w.flags, ++w.epoch, Eout);
+  const int pi = c.prof.begin(c.st, HT_PROF_TRSV);
+  trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout);
+  c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
   hipLaunchKernelGGL(k_count_scaled, dim3(1), dim3(1), 0, c.st, Eout, w.ints + 5);
   if (kk > 0) {
     gemv_t(c.st, L, kk, 1.0, w.V, n, ysol, 0.0, w.tk, w.partials);
@@ -257,7 +315,9 @@ void residual(Ctx& c, int s, int kk, const double* x, const double* rhs) {
   trmv_small(c.st, false, kk, w.T, c.nb, w.tk, 1.0, w.tk2);
   gemv_n(c.st, L, kk, -1.0, w.V, n, w.tk2, 1, 1.0, w.wv, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
+  const int pi = c.prof.begin(c.st, HT_PROF_TRMV);
   trmv_upper(c.st, L, Bp, c.ldb, w.wv, w.w2, w.partials);
+  c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
   gemv_t(c.st, L, kk + 1, 1.0, w.U, n, w.w2, 0.0, w.tk, w.partials);
   trmv_small(c.st, true, kk + 1, w.S, c.nb, w.tk, 1.0, w.tk2);
   gemv_n(c.st, L, kk + 1, -1.0, w.U, n, w.tk2, 1, 1.0, w.w2, w.partials);
@@ -281,7 +341,7 @@ void absorb(Ctx& c, int s, int k) {
   double* V2 = w.V + k;
   for (int t = 1; t <= bl.T; ++t) {
     const int a = bl.rws(t), e = bl.rwe(t);
-    chain_factor(c.st, 1, e - a, k, V2 + a, n, tV(w, 0, t, k), tW(w, 0, t, k), w.Gws);
+    chain(c, 1, false, e - a, k, V2 + a, n, tV(w, 0, t, k), tW(w, 0, t, k));
   }
   const double* L1 = w.V + (L - k);
   const double* V1 = w.V;
@@ -291,7 +351,7 @@ void absorb(Ctx& c, int s, int k) {
   copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
   for (int t = 1; t <= bl.T; ++t) {
     const int a = bl.lws(t), e = bl.lwe(t);
-    chain_factor(c.st, 0, e - a, k, w.Ucp + a, n, tV(w, 2, t, k), tW(w, 2, t, k), w.Gws);
+    chain(c, 0, false, e - a, k, w.Ucp + a, n, tV(w, 2, t, k), tW(w, 2, t, k));
   }
   copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
   copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
@@ -331,7 +391,7 @@ void absorb(Ctx& c, int s, int k) {
     const int r0 = (t == 0) ? 0 : bl.rbs(t);
     const int kr = (t == 0) ? bl.p : k;  // rows of the block
     double* C = at(B, ldb, j + 1 + r0, j + 1 + wn.a);
-    chain_factor_t(c.st, 1, wn.wdt, kr, C, ldb, tV(w, 1, t, k), tW(w, 1, t, k), w.Gws);
+    chain(c, 1, true, wn.wdt, kr, C, ldb, tV(w, 1, t, k), tW(w, 1, t, k));
     right_apply(c, at(B, ldb, 0, j + 1 + wn.a), ldb, j + 1 + r0, wn.wdt, kr, tV(w, 1, t, k),
                 tW(w, 1, t, k));
   }
@@ -383,7 +443,7 @@ void absorb(Ctx& c, int s, int k) {
     const int t = wn.slot;
     const int cs = bl.ds(t), ce = bl.de(t);  // columns d_t
     double* M = at(B, ldb, j + 1 + wn.a, j + 1 + cs);
-    chain_factor(c.st, 0, wn.wdt, ce - cs, M, ldb, tV(w, 3, t, k), tW(w, 3, t, k), w.Gws);
+    chain(c, 0, false, wn.wdt, ce - cs, M, ldb, tV(w, 3, t, k), tW(w, 3, t, k));
     left_apply(c, at(B, ldb, j + 1 + wn.a, j + 1 + ce), ldb, mp - ce, wn.wdt, ce - cs,
                tV(w, 3, t, k), tW(w, 3, t, k));
   }
@@ -470,7 +530,9 @@ int run(Ctx& c) {
       if (kk > 0) gemv_t(st, m, kk, 1.0, w.V + kk, n, vcol, 0.0, w.tk, w.partials);
       wy_append(st, w.T, nb, kk, w.tk, w.dscal + 5);
       double* ycol = at(w.Y, n, 0, kk);
+      const int pi = c.prof.begin(st, HT_PROF_YGEMV);
       gemv_n(st, L, m, 1.0, at(c.A, c.lda, s + 1, j + 1), c.lda, vcol, 1, 0.0, ycol, w.partials);
+      c.prof.end(st, pi, 8.0 * L * (double)m);
       if (kk > 0) gemv_n(st, L, kk, -1.0, w.Y, n, w.tk, 1, 1.0, ycol, w.partials);
       hipLaunchKernelGGL(k_scale_by, dim3((L + 255) / 256), dim3(256), 0, st, ycol, L,
                          w.dscal + 5);
@@ -582,7 +644,7 @@ int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda
     owned = true;
   }
   layout(&w, ni, o.nb, base);
-  (void)hipMemsetAsync(w.flags, 0, ((ni + 63) / 64 + 2) * sizeof(int), st);
+  (void)hipMemsetAsync(w.flags, 0, trsv_flag_bytes(ni), st);
 
   static int* pinned = nullptr;
   if (!pinned) {
@@ -602,6 +664,7 @@ int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda
   c.wantZ = wantZ;
   c.opt = o;
   c.host_ints = pinned;
+  c.prof.on = (o.flags & HT_FLAG_PROFILE) != 0 && stats != nullptr;
   rc = run(c);
   const hipError_t le = hipGetLastError();
   if (rc == 0 && le != hipSuccess) { g_last_hip = le; rc = HT_ERR_HIP; }
@@ -615,6 +678,7 @@ int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda
     stats->absorptions = c.absorptions;
     stats->scaled_solves = pinned[5];
     stats->flops = c.flops;
+    c.prof.collect(stats);
     stats->ms_total = std::chrono::duration<double, std::milli>(
         std::chrono::steady_clock::now() - t0).count();
   }

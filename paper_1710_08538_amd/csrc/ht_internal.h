@@ -18,7 +18,7 @@ void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k,
           double beta, double* C, int ldc);
 
 // y(0:m) = alpha * X(0:m, 0:k) * x + beta * y; x has stride incx.
-// `partials` must hold ceil(k/1024)*m doubles when k > 1024.
+// `partials` must hold ceil(k/512)*m doubles when k > 256.
 void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
             const double* x, int incx, double beta, double* y, double* partials);
 
@@ -26,16 +26,18 @@ void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
 void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
             const double* x, double beta, double* z, double* partials);
 
-// y = B * x for upper triangular B (m x m); y and x distinct.
+// y = B * x for upper triangular B (m x m); y and x distinct; partials as gemv_n.
 void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x,
                 double* y, double* partials);
 
 // Overflow-safe upper triangular solve B x = 2^{-E} c, E >= 0 returned in
-// *E_dev (device int); x distinct from c.  `flags` holds ceil(m/64) ints,
-// `exps` the same; epoch must differ from every earlier call's on `flags`.
+// *E_dev (device int); x distinct from c.  `flags` is a zero-initialised
+// area of trsv_flag_bytes(m) bytes; `epoch` must differ from every earlier
+// call's on the same area.
 void trsv_upper_scaled(hipStream_t st, int m, const double* B, int ldb,
-                       const double* c, double* x, int* exps, int* flags,
-                       int epoch, int* E_dev);
+                       const double* c, double* x, int* flags, int epoch,
+                       int* E_dev);
+size_t trsv_flag_bytes(int m);
 
 // Householder reflector (LAPACK convention): for x of length m at `x`,
 // v (written to `v`, v[0] = 1) and tau with (I - tau v v^T) x = beta e1,

@@ -96,139 +96,6 @@ void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt, con
 }
 
 // ---------------------------------------------------------------------------
-// Overflow-safe upper triangular solve B x = 2^{-E} c.
-//
-// Rows are split into 64-row blocks; block i is solved by one workgroup after
-// the blocks below it have been published (per-block ready flags, no grid
-// barrier).  Each published block carries its own power-of-two exponent e_i
-// (true value = x_i 2^{e_i}), so the solution may span far more than the
-// FP64 range: back substitution with a triangular matrix whose diagonal is
-// small grows geometrically.  Inside a block the substitution runs on one
-// wavefront and rescales by 2^-600 whenever the next entry would exceed
-// 2^600 times its pivot.  A final pass brings all blocks to the largest
-// exponent E (entries smaller by more than the FP64 range become zero) and
-// reports E: only the direction of x enters an opposite reflector (Lemma 2.1).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_trsv(int m, const double* __restrict__ B, int ldb,
-                                              const double* __restrict__ c, double* x, int* exps,
-                                              int* flags, int epoch) {
-  const int nb = (m + 63) >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double red[4][64];
-  for (int ib = nb - 1 - (int)blockIdx.x; ib >= 0; ib -= (int)gridDim.x) {
-    const int r0 = ib << 6;
-    const int nr = min(64, m - r0);
-    const int row = r0 + lane;
-    const bool live = lane < nr;
-    double acc = 0.0;
-    int E = 0;
-    for (int cb = nb - 1; cb > ib; --cb) {
-      if (threadIdx.x == 0) {
-        while (__hip_atomic_load(&flags[cb], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch)
-          __builtin_amdgcn_s_sleep(1);
-      }
-      __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const int ec = __hip_atomic_load(&exps[cb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (ec > E) { acc = ldexp(acc, E - ec); E = ec; }
-      const double f = ldexp(1.0, ec - E);
-      const int cbase = (cb << 6) + wave * 16;
-      if (live) {
-        const double* p = B + (size_t)row;
-#pragma unroll 4
-        for (int q = 0; q < 16; ++q) {
-          const int col = cbase + q;
-          if (col < m) {
-            const double xv = __hip_atomic_load(&x[col], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            acc = fma(p[(size_t)col * ldb], xv * f, acc);
-          }
-        }
-      }
-    }
-    red[wave][lane] = acc;
-    __syncthreads();
-    if (wave == 0) {
-      const double tot = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-      double rhs = live ? (ldexp(c[row], -E) - tot) : 0.0;
-      double Brow[64];
-#pragma unroll
-      for (int q = 0; q < 64; ++q)
-        Brow[q] = (live && q < nr && q > lane) ? B[(size_t)row + (size_t)(r0 + q) * ldb] : 0.0;
-      const double d_own = live ? B[(size_t)row + (size_t)row * ldb] : 1.0;
-      // A zero pivot survives only when ||B||_F = 0 (fix_diagonal replaces
-      // the others); then every direction solves B x = 0 and we take d = 1.
-      const double dinv = (d_own != 0.0) ? 1.0 / d_own : 1.0;
-      int e = E;
-      double xo = 0.0;
-#pragma unroll
-      for (int r = 63; r >= 0; --r) {
-        if (r < nr) {
-          double t = readlane_d(rhs, r);
-          const double dr0 = readlane_d(d_own, r);
-          const double dr = (dr0 != 0.0) ? dr0 : 1.0;
-          int guard = 0;
-          while (!(fabs(t) <= kBig * fabs(dr)) && guard < 8) {
-            rhs *= kShrink;
-            xo *= kShrink;
-            e += kShrinkExp;
-            t = readlane_d(rhs, r);
-            ++guard;
-          }
-          const double xr = t * readlane_d(dinv, r);
-          if (lane == r) xo = xr;
-          rhs = fma(-Brow[r], xr, rhs);
-        }
-      }
-      if (live) __hip_atomic_store(&x[row], xo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (lane == 0) __hip_atomic_store(&exps[ib], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      if (lane == 0) __hip_atomic_store(&flags[ib], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-  }
-}
-
-// Normalise blocks to the largest exponent; E_dev = max exponent.
-__global__ __launch_bounds__(1024) void k_trsv_fin(int m, double* x, const int* exps, int* E_dev) {
-  __shared__ int smax[16];
-  const int nb = (m + 63) >> 6;
-  int e = 0;
-  for (int i = threadIdx.x; i < nb; i += 1024) e = max(e, exps[i]);
-  e = wave_max_i(e);
-  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = e;
-  __syncthreads();
-  int E = 0;
-  for (int i = 0; i < 16; ++i) E = max(E, smax[i]);
-  for (int i = threadIdx.x; i < m; i += 1024) {
-    const int d = exps[i >> 6] - E;
-    if (d != 0) x[i] = ldexp(x[i], d);
-  }
-  if (threadIdx.x == 0) E_dev[0] = E;
-}
-
-static int trsv_grid_cap() {
-  static int cap = 0;
-  if (cap == 0) {
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trsv, 256, 0) != hipSuccess || per < 1)
-      per = 1;
-    cap = per * num_cus();
-  }
-  return cap;
-}
-
-void trsv_upper_scaled(hipStream_t st, int m, const double* B, int ldb, const double* c,
-                       double* x, int* exps, int* flags, int epoch, int* E_dev) {
-  if (m <= 0) return;
-  const int nb = (m + 63) / 64;
-  const int grid = std::min(nb, trsv_grid_cap());
-  void* args[] = {(void*)&m, (void*)&B, (void*)&ldb, (void*)&c, (void*)&x,
-                  (void*)&exps, (void*)&flags, (void*)&epoch};
-  (void)hipLaunchCooperativeKernel((const void*)k_trsv, dim3(grid), dim3(256), args, 0, st);
-  hipLaunchKernelGGL(k_trsv_fin, dim3(1), dim3(1024), 0, st, m, x, exps, E_dev);
-}
-
-// ---------------------------------------------------------------------------
 // Iterative refinement (Sec. 2.3, step c of Sec. 3.2.2).
 // r = 2^{-Erhs} c - w (c = e1 when c == NULL); status = 1 when
 // ||r||_2 <= tol_factor * u * ||B||_F * ||x||_2.  norms[0..1] = ||r||, ||x||.

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "_build", "libhtred.so")
 HT_QZ_IDENTITY, HT_QZ_ACCUMULATE, HT_QZ_NONE = 0, 1, 2
 HT_PREC_FP64, HT_PREC_SPLIT_BF16, HT_PREC_SPLIT_FP8 = 0, 1, 2
 HT_FLAG_CHECK_FINITE = 1
+HT_FLAG_PROFILE = 2
+PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain")
 
 
 class Options(ctypes.Structure):
@@ -31,10 +33,16 @@ class Stats(ctypes.Structure):
     _fields_ = [("columns", ctypes.c_int64), ("cols_extra_ir", ctypes.c_int64),
                 ("ir_steps", ctypes.c_int64), ("ir_failures", ctypes.c_int64),
                 ("absorptions", ctypes.c_int64), ("scaled_solves", ctypes.c_int64),
-                ("flops", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("prof_ms", ctypes.c_double * 8), ("prof_work", ctypes.c_double * 8),
+                ("prof_launches", ctypes.c_int64 * 8)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name.startswith("prof_") else v
+        return d
 
 
 class HTError(RuntimeError):
@@ -116,7 +124,8 @@ def _check(rc):
 
 
 def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
-           prec=HT_PREC_FP64, stats=False, workspace=None, stream=None, check_finite=False):
+           prec=HT_PREC_FP64, stats=False, workspace=None, stream=None, check_finite=False,
+           profile=False):
     """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
 
     A, B: n x n column-major float64 GPU tensors (B upper triangular).
@@ -131,7 +140,8 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
         Z = colmajor_empty(n, device=A.device)
     ldq, ldz = _ld(Q, n, "Q"), _ld(Z, n, "Z")
     o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
-                flags=HT_FLAG_CHECK_FINITE if check_finite else 0)
+                flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
+                | (HT_FLAG_PROFILE if profile else 0))
     st = Stats()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
