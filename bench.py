@@ -130,7 +130,7 @@ def main():
     prof_work = [sum(s["prof_work"][c] for s in stats) for c in range(ncls)]
     prof_l = [sum(s["prof_launches"][c] for s in stats) for c in range(ncls)]
     dom = max(range(ncls), key=lambda c: prof_ms[c])
-    if htred.PROF_CLASSES[dom] in ("wy", "chain"):
+    if htred.PROF_CLASSES[dom] in ("wy", "chain", "sweep"):
         achieved = prof_work[dom] / (prof_ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}

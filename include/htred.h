@@ -83,11 +83,12 @@ typedef struct {
 /* Kernel classes reported in ht_stats.prof_* when HT_FLAG_PROFILE is set.
  * prof_work is the algorithmic work of the class: flops for the
  * contraction classes (WY, CHAIN), bytes for the streaming classes. */
-#define HT_PROF_WY     0  /* block-reflector updates of A, B, Q, Z (flops) */
+#define HT_PROF_WY     0  /* block-reflector updates by general products (flops) */
 #define HT_PROF_TRSV   1  /* triangular solves with B (bytes of B read) */
 #define HT_PROF_TRMV   2  /* residual products with B (bytes of B read) */
 #define HT_PROF_YGEMV  3  /* Y = A V T columns (bytes of A read) */
 #define HT_PROF_CHAIN  4  /* QL/QR/RQ chain factorisations (flops) */
+#define HT_PROF_SWEEP  5  /* fused MFMA sweeps of chain windows over rows (flops) */
 #define HT_PROF_NCLASS 8
 
 typedef struct {

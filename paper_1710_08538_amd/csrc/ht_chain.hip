@@ -4,148 +4,248 @@
 // restoring it from the right (step e), QR when restoring it from the left
 // (step f).  RQ is done as QL of the transposed block.
 //
-// One workgroup (1024 threads for k <= 64, 512 for k <= 128) factors one
-// w x k tile (w <= 2*KMAX, k <= KMAX)
-// held in registers: thread (c, g) owns column c, rows g*RPG .. g*RPG+RPG-1.
-// The orthogonal factor is returned in regular WY form Qf = I - V W^T
-// (Sec. 2.4), reflectors in the order they are computed, so that
+// One workgroup factors one w x k tile (w <= 2 KMAX, k <= KMAX) held in
+// registers.  The orthogonal factor is returned in regular WY form
+// Qf = I - V W^T (Sec. 2.4), reflectors in the order they are computed, so
 //   QR:  tile = Qf [R; 0],   QL:  tile = Qf [0; L].
 // W is accumulated alongside the factorisation:  with Qf_i = I - V_i W_i^T,
 //   Qf_i (I - tau v v^T) = I - [V_i v] [(I - tau v v^T) W_i, tau v]^T,
-// so after column c has produced its reflector the registers that held
-// column c of the tile hold column c of W and receive the later reflectors
-// exactly like the columns still to be reduced.  Each reflector costs three
-// workgroup barriers; one wavefront forms the reflector, everyone applies it.
+// so once column c has produced its reflector, the registers that held it
+// hold column c of W and take the later reflectors like the columns still
+// to be reduced.
+//
+// Register layout.  KMAX/8 wavefronts; in each, lane l = 32 h + r_l works on
+// rows r_l RQ .. r_l RQ + RQ-1 (RQ = 2 KMAX / 32) of the four columns
+// 8 wave + 4 h + (0..3).  A wavefront thus spans all rows, and the column
+// sums of a reflector step are reduced inside each 32-lane half with DPP row
+// operations and v_permlane16_swap, without LDS.  Per reflector:
+//   1. the wavefront owning column i reduces its norm, forms the reflector
+//      (sign convention of LAPACK's dlarfg: beta = -sign(alpha) ||x||) and
+//      writes v to one of two LDS buffers;
+//   2. one workgroup barrier;
+//   3. every wavefront reads v for its rows, forms the four column dots,
+//      reduces them and applies the rank-1 update.
+// The owner of column i+1 proceeds to step 1 of the next reflector as soon as
+// its own update is done; the double buffer makes the single barrier enough.
 #include "ht_device.h"
 #include "ht_internal.h"
 
 namespace htk {
 
+namespace {
+
 __device__ __forceinline__ size_t tidx(int r, int c, int ld, int trans) {
   return trans ? ((size_t)c + (size_t)r * ld) : ((size_t)r + (size_t)c * ld);
 }
 
-template <int KMAX, int NT>
-__global__ __launch_bounds__(NT) void k_chain_reg(int mode, int w, int k, double* __restrict__ X,
-                                                    int ldx, int trans, double* __restrict__ Vout,
-                                                    double* __restrict__ Wout) {
-  constexpr int G = NT / KMAX;          // row groups
-  constexpr int RPG = 2 * KMAX / G;     // rows per group
-  constexpr int WR = 2 * KMAX / 64;     // rows per lane when one wave scans a column
-  static_assert(RPG <= 64, "a group's rows must fit one wavefront");
-  __shared__ double vraw[2 * KMAX];
-  __shared__ double vfin[2 * KMAX];
-  __shared__ double sref[1];            // tau
-  __shared__ double pdot[G][KMAX];
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// DPP controls: quad_perm [1,0,3,2] (lane ^ 1), quad_perm [2,3,0,1]
+// (lane ^ 2), row_half_mirror (lane i of 8 <- 7 - i), row_mirror (lane i of
+// 16 <- 15 - i).  Applied in this order, each step combines disjoint groups,
+// so after the four steps every lane of a 16-lane row holds the row's result.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+__device__ __forceinline__ double row_sum16(double x) {
+  x += dpp_d<kDppXor1>(x);
+  x += dpp_d<kDppXor2>(x);
+  x += dpp_d<kDppHalfMirror>(x);
+  x += dpp_d<kDppMirror>(x);
+  return x;
+}
+__device__ __forceinline__ double row_max16(double x) {
+  x = fmax(x, dpp_d<kDppXor1>(x));
+  x = fmax(x, dpp_d<kDppXor2>(x));
+  x = fmax(x, dpp_d<kDppHalfMirror>(x));
+  x = fmax(x, dpp_d<kDppMirror>(x));
+  return x;
+}
+
+// v_permlane16_swap on a pair of doubles: for each pair of 16-lane rows
+// (0,1) and (2,3), row 1 of x and row 0 of y trade places.  Afterwards
+//   x = {row e: x_e,  row o: y_e},   y = {row e: x_o,  row o: y_o}.
+__device__ __forceinline__ void swap16(double& x, double& y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false,
+                                                   false);
+  x = __hiloint2double((int)hi[0], (int)lo[0]);
+  y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Sum / max over each 32-lane half, result in every lane of the half.
+__device__ __forceinline__ double half_sum(double x) {
+  x = row_sum16(x);
+  double y = x;
+  swap16(x, y);
+  return x + y;
+}
+__device__ __forceinline__ double half_max(double x) {
+  x = row_max16(x);
+  double y = x;
+  swap16(x, y);
+  return fmax(x, y);
+}
+
+}  // namespace
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int KMAX>
+__global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
+                                                       double* __restrict__ X, int ldx, int trans,
+                                                       double* __restrict__ Vout,
+                                                       double* __restrict__ Wout) {
+  constexpr int RQ = 2 * KMAX / 32;  // rows per lane
+  constexpr int CJ = 4;              // columns per lane
+  __shared__ double vbuf[2][2 * KMAX];
+  __shared__ double tbuf[2];
 
   const int tid = threadIdx.x;
-  const int c = tid % KMAX;
-  const int g = tid / KMAX;
-  const int lane = tid & 63;
-  const int r0 = g * RPG;
-  (void)lane;
-  const bool colok = c < k;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int h = lane >> 5, rl = lane & 31;
+  const int rbase = rl * RQ;
+  const int cbase = 8 * wv + 4 * h;
 
-  double reg[RPG];
+  // reg[q][j]: row rbase + q, column cbase + j (a 4-vector per row, so that
+  // the owner can pick column i's entries by a vector element select)
+  v4d reg[RQ];
 #pragma unroll
-  for (int q = 0; q < RPG; ++q) {
-    const int r = r0 + q;
-    reg[q] = (colok && r < w) ? X[tidx(r, c, ldx, trans)] : 0.0;
-  }
+  for (int q = 0; q < RQ; ++q)
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      const int r = rbase + q, c = cbase + j;
+      reg[q][j] = (r < w && c < k) ? X[tidx(r, c, ldx, trans)] : 0.0;
+    }
 
-  for (int step = 0; step < k; ++step) {
+  // Step 1 for the reflector of `step`, run by the owning wavefront only.
+  auto form = [&](int step) __attribute__((always_inline)) {
     const int i = (mode == 0) ? step : (k - 1 - step);
     const int p = (mode == 0) ? i : (w - k + i);
     const int x0 = (mode == 0) ? p + 1 : 0;  // x-part rows [x0, x1)
     const int x1 = (mode == 0) ? w : p;
-    // phase A: the owners of column i publish it
-    if (c == i) {
+    const int ji = i & 3, hi = (i >> 2) & 1;
+    double x[RQ];
 #pragma unroll
-      for (int q = 0; q < RPG; ++q) vraw[r0 + q] = reg[q];
+    for (int q = 0; q < RQ; ++q) {  // select tree (no indexed register access)
+      const double a = (ji & 1) ? reg[q][1] : reg[q][0];
+      const double b = (ji & 1) ? reg[q][3] : reg[q][2];
+      x[q] = (ji & 2) ? b : a;
     }
-    __syncthreads();
-    // phase A2: wave 0 forms the reflector and the final v
-    if (tid < 64) {
-      double xv[WR];
-      double amax = 0.0, ss = 0.0;
+    double ss = 0.0, am = 0.0, ap = 0.0;
 #pragma unroll
-      for (int q = 0; q < WR; ++q) {
-        const int r = lane + 64 * q;
-        xv[q] = (r >= x0 && r < x1) ? vraw[r] : 0.0;
-        amax = fmax(amax, fabs(xv[q]));
-        ss = fma(xv[q], xv[q], ss);
+    for (int q = 0; q < RQ; ++q) {
+      const int r = rbase + q;
+      const double xv = (r >= x0 && r < x1) ? x[q] : 0.0;
+      am = fmax(am, fabs(xv));
+      ss = fma(xv, xv, ss);
+      if (q == p % RQ) ap = x[q];
+    }
+    ss = readlane_d(half_sum(ss), 32 * hi);
+    am = readlane_d(half_max(am), 32 * hi);
+    const double alpha = readlane_d(ap, 32 * hi + p / RQ);
+    double xnorm;
+    if (am == 0.0) {
+      xnorm = 0.0;
+    } else if (am > 0x1.0p-450 && am < 0x1.0p450) {
+      xnorm = sqrt(ss);
+    } else {  // rescaled second pass near the ends of the FP64 range
+      const double inv = 1.0 / am;
+      double s2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const int r = rbase + q;
+        const double t = (r >= x0 && r < x1) ? x[q] * inv : 0.0;
+        s2 = fma(t, t, s2);
       }
-      amax = wave_max(amax);
-      ss = wave_sum(ss);
-      double xnorm;
-      if (amax == 0.0) {
-        xnorm = 0.0;
-      } else if (amax > 0x1.0p-450 && amax < 0x1.0p450) {
-        xnorm = sqrt(ss);
-      } else {  // rescaled second pass near the ends of the FP64 range
-        const double inv = 1.0 / amax;
-        double s2 = 0.0;
+      xnorm = am * sqrt(readlane_d(half_sum(s2), 32 * hi));
+    }
+    const Refl rf = make_refl(alpha, xnorm);
+    if (h == hi) {
+      double* vb = vbuf[step & 1];
 #pragma unroll
-        for (int q = 0; q < WR; ++q) { const double t = xv[q] * inv; s2 = fma(t, t, s2); }
-        xnorm = amax * sqrt(wave_sum(s2));
-      }
-      const Refl rf = make_refl(vraw[p], xnorm);
-#pragma unroll
-      for (int q = 0; q < WR; ++q) {
-        const int r = lane + 64 * q;
-        const double v = (r == p) ? 1.0 : xv[q] * rf.scal;
-        vfin[r] = v;
+      for (int q = 0; q < RQ; ++q) {
+        const int r = rbase + q;
+        const bool inx = r >= x0 && r < x1;
+        const double v = (r == p) ? 1.0 : (inx ? x[q] * rf.scal : 0.0);
+        vb[r] = v;
         if (r < w) {
           // column i of the factor (R or L) and reflector `step`
-          double out = vraw[r];
-          if (r == p) out = rf.beta;
-          else if (r >= x0 && r < x1) out = 0.0;
-          X[tidx(r, i, ldx, trans)] = out;
+          X[tidx(r, i, ldx, trans)] = (r == p) ? rf.beta : (inx ? 0.0 : x[q]);
           Vout[(size_t)r + (size_t)step * w] = v;
         }
       }
-      if (lane == 0) sref[0] = rf.tau;
+      if (rl == 0) tbuf[step & 1] = rf.tau;
     }
+  };
+
+  if (wv == (((mode == 0) ? 0 : (k - 1)) >> 3)) form(0);
+
+  for (int step = 0; step < k; ++step) {
+    const int i = (mode == 0) ? step : (k - 1 - step);
     __syncthreads();
-    const double tau = sref[0];
-    // v of this group's rows, read from LDS (the same address in every lane)
-    const double* vg = vfin + r0;
-    if (c == i) {
+    const double tau = tbuf[step & 1];
+    double v[RQ];
 #pragma unroll
-      for (int q = 0; q < RPG; ++q) reg[q] = tau * vg[q];  // column `step` of W
-      pdot[g][c] = 0.0;
+    for (int q = 0; q < RQ; ++q) v[q] = vbuf[step & 1][rbase + q];
+    double d[CJ];
+#pragma unroll
+    for (int j = 0; j < CJ; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) s = fma(v[q], reg[q][j], s);
+      d[j] = s;
+    }
+    // reduce the four column dots over the 32 lanes of each half:
+    // pairwise across the two rows (scattering d0/d1 and d2/d3 to the even
+    // and odd rows), across each row, then gathered back into every lane
+    swap16(d[0], d[1]);
+    swap16(d[2], d[3]);
+    double e0 = row_sum16(d[0] + d[1]);
+    double e1 = row_sum16(d[2] + d[3]);
+    double f0 = e0, f1 = e1;
+    swap16(e0, f0);  // e0 = sum of column 0 everywhere, f0 = column 1
+    swap16(e1, f1);
+    const double dd[CJ] = {e0, f0, e1, f1};
+    if (wv == (i >> 3)) {
+      // the owner wavefront: column i becomes column `step` of W
+#pragma unroll
+      for (int j = 0; j < CJ; ++j) {
+        const bool isi = (cbase + j) == i;
+        const double f = tau * dd[j];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) reg[q][j] = isi ? tau * v[q] : fma(-f, v[q], reg[q][j]);
+      }
     } else {
-      double d = 0.0;
 #pragma unroll
-      for (int q = 0; q < RPG; ++q) {
-        d = fma(vg[q], reg[q], d);
-        if ((q & 7) == 7) __asm__ volatile("" ::: "memory");  // keep LDS reads in chunks
+      for (int j = 0; j < CJ; ++j) {
+        const double f = tau * dd[j];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) reg[q][j] = fma(-f, v[q], reg[q][j]);
       }
-      pdot[g][c] = d;
     }
-    __syncthreads();
-    // phase C: rank-1 update of every other column (tile or W)
-    if (c != i && colok) {
-      double d = 0.0;
-#pragma unroll
-      for (int h = 0; h < G; ++h) d += pdot[h][c];
-      const double f = tau * d;
-      if (f != 0.0) {
-#pragma unroll
-        for (int q = 0; q < RPG; ++q) {
-          reg[q] = fma(-f, vg[q], reg[q]);
-          if ((q & 7) == 7) __asm__ volatile("" ::: "memory");
-        }
-      }
+    if (step + 1 < k) {
+      const int in = (mode == 0) ? step + 1 : (k - 2 - step);
+      if (wv == (in >> 3)) form(step + 1);
     }
   }
+
   // registers now hold W; column c was produced at step s(c)
-  if (colok) {
-    const int sc = (mode == 0) ? c : (k - 1 - c);
 #pragma unroll
-    for (int q = 0; q < RPG; ++q) {
-      const int r = r0 + q;
-      if (r < w) Wout[(size_t)r + (size_t)sc * w] = reg[q];
+  for (int j = 0; j < CJ; ++j) {
+    const int c = cbase + j;
+    if (c < k) {
+      const int sc = (mode == 0) ? c : (k - 1 - c);
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const int r = rbase + q;
+        if (r < w) Wout[(size_t)r + (size_t)sc * w] = reg[q][j];
+      }
     }
   }
 }
@@ -154,11 +254,11 @@ static void launch_chain(hipStream_t st, int mode, int w, int k, double* tile, i
                          double* Vout, double* Wout) {
   if (w <= 0 || k <= 0) return;
   if (k <= 64 && w <= 128)
-    hipLaunchKernelGGL((k_chain_reg<64, 1024>), dim3(1), dim3(1024), 0, st, mode, w, k, tile,
-                       ldt, trans, Vout, Wout);
+    hipLaunchKernelGGL((k_chain_reg<64>), dim3(1), dim3(512), 0, st, mode, w, k, tile, ldt, trans,
+                       Vout, Wout);
   else
-    hipLaunchKernelGGL((k_chain_reg<128, 1024>), dim3(1), dim3(1024), 0, st, mode, w, k, tile,
-                       ldt, trans, Vout, Wout);
+    hipLaunchKernelGGL((k_chain_reg<128>), dim3(1), dim3(1024), 0, st, mode, w, k, tile, ldt,
+                       trans, Vout, Wout);
 }
 
 void chain_factor(hipStream_t st, int mode, int w, int k, double* tile, int ldt, double* Vout,

@@ -16,6 +16,7 @@
 
 #include "../../include/htred.h"
 #include "ht_internal.h"
+#include "ht_sweep.h"
 
 using namespace htk;
 
@@ -236,15 +237,84 @@ std::vector<Win> left_windows(const Blocks& bl, int chain) {
   return v;
 }
 
-// Right sweep of a chain over X(0:rows, j+1 : n).  For an upper triangular
-// X (B), rows below a window's last column are zero and are skipped.
+// A matrix (or row range) receiving a right sweep: rows 0..rows-1 of X,
+// absolute column indices; `tri` marks an upper triangular X (B), whose rows
+// below a window's last column are zero there.
+struct RJob { double* X; int ld; int rows; bool tri; int tri_off; };
+
+// Apply the windows of a chain, in order, as right multiplications
+// X(:, j+1+win) <- X(:, j+1+win) (I - V W^T) to every job.  Runs of
+// consecutive full windows (width 2k, moving by k) go to the fused MFMA
+// sweep kernel in one launch for all jobs; the odd windows at the ends of a
+// chain (first window p+k wide, last one p x p) use the generic product.
+void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, int chain,
+                const std::vector<Win>& wins) {
+  const int k = bl.k;
+  size_t i = 0;
+  while (i < wins.size()) {
+    const Win& w0 = wins[i];
+    const bool full = sweep_supported(k) && jobs.size() <= 4 && w0.wdt == 2 * k && w0.k == k;
+    size_t e = i + 1;
+    int dir = 0;
+    if (full) {
+      while (e < wins.size() && wins[e].wdt == 2 * k && wins[e].k == k) {
+        const int d = wins[e].a - wins[e - 1].a;
+        if (!((d == k || d == -k) && (dir == 0 || d == dir * k))) break;
+        dir = d > 0 ? 1 : -1;
+        ++e;
+      }
+    }
+    if (full && e - i >= 2) {
+      SweepArgs sa;
+      memset(&sa, 0, sizeof(sa));
+      int wg = 0;
+      for (const RJob& jb : jobs) {
+        if (jb.rows <= 0) continue;
+        SweepJob& sj = sa.job[sa.njobs++];
+        sj.X = jb.X;
+        sj.ld = jb.ld;
+        sj.nrows = jb.rows;
+        sj.tri = jb.tri ? 1 : 0;
+        sj.tri_off = jb.tri_off;
+        sj.wg0 = wg;
+        wg += (jb.rows + 63) / 64;
+      }
+      sa.nwin = (int)(e - i);
+      sa.c0 = j + 1 + w0.a;
+      sa.Vp = c.w->pool[chain][0];
+      sa.Wp = c.w->pool[chain][1];
+      sa.slot0 = w0.slot;
+      sa.slot_step = wins[i + 1].slot - w0.slot;
+      double fl = 0.0;
+      for (const RJob& jb : jobs) {
+        if (jb.rows <= 0) continue;
+        for (size_t t = i; t < e; ++t) {  // B: rows below a window's end are zero
+          const int r = jb.tri ? std::max(0, std::min(jb.rows, j + 1 + wins[t].a + 2 * k - jb.tri_off))
+                               : jb.rows;
+          fl += 8.0 * r * (double)k * k;
+        }
+      }
+      const int pi = c.prof.begin(c.st, HT_PROF_SWEEP);
+      sweep_rows(c.st, sa, k, dir);
+      c.prof.end(c.st, pi, fl);
+      c.flops += fl;
+      i = e;
+      continue;
+    }
+    for (const RJob& jb : jobs) {
+      if (jb.rows <= 0) continue;
+      const int r = jb.tri ? std::min(jb.rows, j + 1 + w0.a + w0.wdt - jb.tri_off) : jb.rows;
+      right_apply(c, at(jb.X, jb.ld, 0, j + 1 + w0.a), jb.ld, r, w0.wdt, w0.k,
+                  tV(*c.w, chain, w0.slot, k), tW(*c.w, chain, w0.slot, k));
+    }
+    ++i;
+  }
+}
+
+// Right sweep of a chain over X(0:rows, j+1 : n).
 void sweep_right(Ctx& c, double* X, int ld, int rows, bool tri, int j, const Blocks& bl,
                  int chain) {
-  for (const Win& wn : right_windows(bl, chain)) {
-    const int r = tri ? std::min(rows, j + 1 + wn.a + wn.wdt) : rows;
-    right_apply(c, at(X, ld, 0, j + 1 + wn.a), ld, r, wn.wdt, wn.k, tV(*c.w, chain, wn.slot, bl.k),
-                tW(*c.w, chain, wn.slot, bl.k));
-  }
+  sweep_jobs(c, {RJob{X, ld, rows, tri, 0}}, j, bl, chain, right_windows(bl, chain));
 }
 
 // Left sweep of a chain over rows j+1.. of X, columns [c0, n).  With
@@ -259,13 +329,11 @@ void sweep_left(Ctx& c, double* X, int ld, int c0, bool tri, int j, const Blocks
 
 // Q(:, j+1 : n) <- Q * (chain transforms in order).
 void sweep_cols_right(Ctx& c, double* X, int ld, int rows, int j, const Blocks& bl, int chain) {
-  for (const Win& wn : left_windows(bl, chain))
-    right_apply(c, at(X, ld, 0, j + 1 + wn.a), ld, rows, wn.wdt, wn.k,
-                tV(*c.w, chain, wn.slot, bl.k), tW(*c.w, chain, wn.slot, bl.k));
+  sweep_jobs(c, {RJob{X, ld, rows, false, 0}}, j, bl, chain, left_windows(bl, chain));
 }
 
 // One chain factorisation, timed as HT_PROF_CHAIN (flops of a Householder
-// QR/QL of a wdt x k tile plus the T/W build: about 4 wdt k^2).
+// QR/QL of a wdt x k tile plus the W build: about 4 wdt k^2).
 void chain(Ctx& c, int mode, bool trans, int wdt, int k, double* tile, int ld, double* Vf,
            double* Wf) {
   const int pi = c.prof.begin(c.st, HT_PROF_CHAIN);
@@ -364,9 +432,14 @@ void absorb(Ctx& c, int s, int k) {
   rts.push_back({B, ldb, n, true});
   if (c.wantZ) rts.push_back({c.Z, c.ldz, n, false});
   rts.push_back({A, lda, s + 1, false});
+  {
+    std::vector<RJob> jobs;
+    for (auto& rt : rts) jobs.push_back(RJob{rt.X, rt.ld, rt.rows, rt.tri, 0});
+    jobs.push_back(RJob{at(A, lda, s + 1, 0), lda, L, false, s + 1});
+    sweep_jobs(c, jobs, j, bl, 0, right_windows(bl, 0));
+  }
   for (auto& rt : rts) {
     if (rt.rows <= 0) continue;
-    sweep_right(c, rt.X, rt.ld, rt.rows, rt.tri, j, bl, 0);
     double* Xs = at(rt.X, rt.ld, 0, s + 1);
     double* Xe = at(rt.X, rt.ld, 0, n - k);
     gemm(c.st, false, false, rt.rows, k, k, 1.0, Xs, rt.ld, V1, n, 0.0, w.Wk, n);
@@ -378,7 +451,6 @@ void absorb(Ctx& c, int s, int k) {
   }
   // rows s+1..n-1 of A through Y = A V T (Sec. 3.3.1 e):
   //   A(:, j+1:n) <- A Q^;  A(:, j) -= Y V1(k-1,:)^T;  A(:, n-k:n) -= Y L1^T.
-  sweep_right(c, at(A, lda, s + 1, 0), lda, L, false, j, bl, 0);
   gemv_n(c.st, L, k, -1.0, w.Y, n, w.V + (k - 1), n, 1.0, at(A, lda, s + 1, j), w.partials);
   gemm(c.st, false, true, L, k, k, -1.0, w.Y, n, L1, n, 1.0, at(A, lda, s + 1, n - k), lda);
   c.flops += 4.0 * L * (double)k * k;
@@ -395,8 +467,11 @@ void absorb(Ctx& c, int s, int k) {
     right_apply(c, at(B, ldb, 0, j + 1 + wn.a), ldb, j + 1 + r0, wn.wdt, kr, tV(w, 1, t, k),
                 tW(w, 1, t, k));
   }
-  sweep_right(c, A, lda, n, false, j, bl, 1);
-  if (c.wantZ) sweep_right(c, c.Z, c.ldz, n, false, j, bl, 1);
+  {
+    std::vector<RJob> jobs{RJob{A, lda, n, false, 0}};
+    if (c.wantZ) jobs.push_back(RJob{c.Z, c.ldz, n, false, 0});
+    sweep_jobs(c, jobs, j, bl, 1, right_windows(bl, 1));
+  }
 
   // (3.3.2 c) spike columns s+1..j of B:
   //   B(s+1:j+1, s+1:j+1) -= U1 S^T (U^T B(s+1:n, s+1:j+1));  B(j+1:n, s+1:j+1) = 0.

@@ -18,7 +18,7 @@ HT_QZ_IDENTITY, HT_QZ_ACCUMULATE, HT_QZ_NONE = 0, 1, 2
 HT_PREC_FP64, HT_PREC_SPLIT_BF16, HT_PREC_SPLIT_FP8 = 0, 1, 2
 HT_FLAG_CHECK_FINITE = 1
 HT_FLAG_PROFILE = 2
-PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain")
+PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain", "sweep")
 
 
 class Options(ctypes.Structure):
