@@ -79,6 +79,8 @@ typedef struct {
 /* flags */
 #define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs) */
 #define HT_FLAG_PROFILE      2  /* time kernel classes with HIP events (stats) */
+#define HT_FLAG_SOLVE_SOLO   4  /* triangular solves on one workgroup, without
+                                   helper workgroups (slower; for testing) */
 
 /* Kernel classes reported in ht_stats.prof_* when HT_FLAG_PROFILE is set.
  * prof_work is the algorithmic work of the class: flops for the

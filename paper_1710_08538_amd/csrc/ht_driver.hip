@@ -361,7 +361,8 @@ void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, i
   gemv_n(c.st, L, nu, -1.0, w.U, n, w.tk2, 1, 1.0, ctil, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRSV);
-  trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout);
+  trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout,
+                    (c.opt.flags & HT_FLAG_SOLVE_SOLO) != 0);
   c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
   hipLaunchKernelGGL(k_count_scaled, dim3(1), dim3(1), 0, c.st, Eout, w.ints + 5);
   if (kk > 0) {

@@ -33,10 +33,11 @@ void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x
 // Overflow-safe upper triangular solve B x = 2^{-E} c, E >= 0 returned in
 // *E_dev (device int); x distinct from c.  `flags` is a zero-initialised
 // area of trsv_flag_bytes(m) bytes; `epoch` must differ from every earlier
-// call's on the same area.
+// call's on the same area, and successive calls on one area must be ordered
+// (one stream).  `solo` launches the solver alone (no helper workgroups).
 void trsv_upper_scaled(hipStream_t st, int m, const double* B, int ldb,
                        const double* c, double* x, int* flags, int epoch,
-                       int* E_dev);
+                       int* E_dev, bool solo = false);
 size_t trsv_flag_bytes(int m);
 
 // Householder reflector (LAPACK convention): for x of length m at `x`,

@@ -48,10 +48,12 @@ struct TrsvArgs {
   const double* B;
   int ldb;
   const double* c;
-  double* x;        // plain copy of the solution blocks (for later kernels)
-  int* exps;        // plain copy of the block exponents
+  double* x;        // solution (plain stores; rescaled to one exponent at the end)
+  int* exps;        // block exponents (plain stores)
   uint64_t* xll;    // published x blocks (epoch-tagged words)
   uint64_t* all;    // published far sums
+  int* ctl;         // role and row tickets, two sets used by alternate epochs
+  int* E_dev;       // exponent of the result
   uint32_t epoch;
 };
 
@@ -77,50 +79,97 @@ __device__ __forceinline__ void publish_block(uint64_t* blk, uint32_t epoch, dou
 }
 
 // This thread's part of tile B(block row ib, block column cb):
-// t[q] = B(64 ib + lane, 64 cb + kCPW wave + q); zero outside the matrix and,
-// for the diagonal block, below the diagonal.  Addresses are clamped so every
-// load is in bounds and no load sits behind a branch.
-__device__ __forceinline__ void load_tile(const TrsvArgs& a, int ib, int cb, bool diag, int lane,
+// t[q] = B(64 ib + lane, 64 cb + kCPW wave + q).  Addresses are clamped into
+// the matrix and the loads carry no condition, so they all issue back to
+// back; the entries outside the matrix (and below the diagonal of a diagonal
+// tile) are zeroed by mask_tile when the values are used.
+__device__ __forceinline__ void load_tile(const TrsvArgs& a, int ib, int cb, int lane, int wave,
+                                          double t[kCPW]) {
+  const int rowc = min(ib * 64 + lane, a.m - 1);
+  const int cbase = cb * 64 + wave * kCPW;
+#pragma unroll
+  for (int q = 0; q < kCPW; ++q) {
+    const int colc = min(max(cbase + q, 0), a.m - 1);
+    t[q] = a.B[(size_t)rowc + (size_t)colc * a.ldb];
+  }
+}
+__device__ __forceinline__ void mask_tile(const TrsvArgs& a, int ib, int cb, bool diag, int lane,
                                           int wave, double t[kCPW]) {
   const int row = ib * 64 + lane;
-  const int rowc = min(row, a.m - 1);
   const int cbase = cb * 64 + wave * kCPW;
 #pragma unroll
   for (int q = 0; q < kCPW; ++q) {
     const int col = cbase + q;
     const bool ok = row < a.m && col < a.m && cb >= 0 && (!diag || col >= row);
-    const int colc = min(max(col, 0), a.m - 1);
-    const double v = a.B[(size_t)rowc + (size_t)colc * a.ldb];
-    t[q] = ok ? v : 0.0;
+    t[q] = ok ? t[q] : 0.0;
+  }
+}
+
+// Stage a masked diagonal tile in LDS twice: dgu as is, dgs with column c
+// divided by its pivot and the pivot itself replaced by 0, so that the fast
+// substitution needs one FMA per row.  Rows beyond the matrix get pivot 1
+// and no coupling.  A zero pivot survives only when ||B||_F = 0; any
+// direction then works, and it is treated as 1.
+__device__ __forceinline__ void stage_diag(const double t[kCPW], int lane, int wave, double* dgu,
+                                           double* dgs) {
+  // the wavefront's kCPW pivots, gathered into lanes 0..kCPW-1 so that one
+  // division serves them all
+  double piv = 1.0;
+#pragma unroll
+  for (int q = 0; q < kCPW; ++q) {
+    const double d = readlane_d(t[q], wave * kCPW + q);
+    if (lane == q) piv = d;
+  }
+  const double inv = (piv != 0.0) ? 1.0 / piv : 1.0;
+#pragma unroll
+  for (int q = 0; q < kCPW; ++q) {
+    const int c = wave * kCPW + q;
+    const double dinv = readlane_d(inv, q);
+    dgu[c * kTLD + lane] = t[q];
+    dgs[c * kTLD + lane] = (lane < c) ? t[q] * dinv : 0.0;
   }
 }
 
 // Back substitution of one 64-row diagonal block on one wavefront: lane l
-// holds row l of the right-hand side; dg is the block (column-major, leading
-// dimension kTLD) in LDS.  Returns the lane's entry of x and updates the
-// block exponent e.  The fast pass assumes no entry exceeds 2^600 times its
-// pivot; if any entry of the result is that large or not finite, the block is
-// redone with a per-row rescaling by 2^-600.
-__device__ __forceinline__ double diag_solve(double rhs0, const double* dg, int nr, int lane,
-                                             int& e) {
+// holds row l of the right-hand side (rows >= nr hold zeros).  Returns the
+// lane's entry of x and updates the block exponent e.  The fast pass runs
+// rhs_i -= (B_ir / B_rr) rhs_r down the rows and divides at the end; if any
+// entry of the result exceeds 2^600 or is not finite, the block is redone
+// from the unscaled tile with a per-row rescaling by 2^-600.
+__device__ __forceinline__ double diag_solve(double rhs0, const double* dgu, const double* dgs,
+                                             int nr, int lane, int& e) {
   const bool live = lane < nr;
-  const double d_own = live ? dg[lane * kTLD + lane] : 1.0;
-  // a zero pivot survives only when ||B||_F = 0; any direction then works
+  const double d_own = live ? dgu[lane * kTLD + lane] : 1.0;
   const double dinv = (d_own != 0.0) ? 1.0 / d_own : 1.0;
-  double rhs = rhs0, xo = 0.0;
+  // The scaled couplings are read from LDS 8 rows at a time, one chunk
+  // ahead of the substitution (the empty asm statements keep the compiler
+  // from sinking the reads next to their uses), so the dependency chain per
+  // row is a readlane and an FMA.  Row 0 has no coupling (its column is 0).
+  double rhs = rhs0;
+  double ca[8], cb[8];
 #pragma unroll
-  for (int r = 63; r >= 0; --r) {
-    if (r < nr) {
-      const double xr = readlane_d(rhs, r) * readlane_d(dinv, r);
-      if (lane == r) xo = xr;
-      rhs = fma(-dg[r * kTLD + lane], xr, rhs);
+  for (int i = 0; i < 8; ++i) ca[i] = dgs[(63 - i) * kTLD + lane];
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    const int rtop = 63 - 8 * ch;
+    __asm__ volatile("" ::: "memory");
+    if (ch + 1 < 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) cb[i] = dgs[(rtop - 8 - i) * kTLD + lane];
     }
+    __asm__ volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (rtop - i >= 1) rhs = fma(-ca[i], readlane_d(rhs, rtop - i), rhs);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ca[i] = cb[i];
   }
-  const bool bad = live && !(fabs(xo) <= kBig);
-  if (!__any(bad)) return live ? xo : 0.0;
+  const double xf = rhs * dinv;
+  const bool bad = live && !(fabs(xf) <= kBig);
+  if (!__any(bad)) return live ? xf : 0.0;
   // careful pass
   rhs = rhs0;
-  xo = 0.0;
+  double xo = 0.0;
   for (int r = nr - 1; r >= 0; --r) {
     double t = readlane_d(rhs, r);
     const double dr0 = readlane_d(d_own, r);
@@ -135,39 +184,78 @@ __device__ __forceinline__ double diag_solve(double rhs0, const double* dg, int 
     }
     const double xr = t * readlane_d(dinv, r);
     if (lane == r) xo = xr;
-    rhs = fma(-dg[r * kTLD + lane], xr, rhs);
+    rhs = fma(-dgu[r * kTLD + lane], xr, rhs);
   }
   return live ? xo : 0.0;
 }
 
-__global__ __launch_bounds__(kNT) void k_trsv_la(TrsvArgs a) {
+// Far sum of block row r, sum over block columns cb >= r+kLA+1 of
+// B(r, cb) x_cb, computed by one wavefront from the published x words.  The
+// solver falls back to this when no helper has taken the row (for instance
+// when no other workgroup of the launch is resident).
+__device__ double far_sum_wave(const TrsvArgs& a, int r, int nb, int lane, int& E) {
+  double acc = 0.0;
+  E = 0;
+  const int row = r * 64 + lane;  // r < nb - 1: a full block row
+  for (int cb = nb - 1; cb >= r + 1 + kLA; --cb) {
+    const uint64_t* blk = a.xll + (size_t)cb * kWords;
+    const int ec = (int)(uint32_t)ld_word(blk + 128);
+    double s = 0.0;
+    for (int j = 0; j < 64; ++j) {
+      const int col = cb * 64 + j;
+      if (col < a.m) {
+        const double xv = join_words(ld_word(blk + 2 * j), ld_word(blk + 2 * j + 1));
+        s = fma(a.B[(size_t)row + (size_t)col * a.ldb], xv, s);
+      }
+    }
+    if (ec > E) { acc = ldexp(acc, E - ec); E = ec; }
+    acc = fma(s, ldexp(1.0, ec - E), acc);
+  }
+  return acc;
+}
+
+// One launch solves the system.  The first workgroup to start takes the
+// solver role (a ticket from ctl), the others are helpers that take block
+// rows from a second ticket.  Nothing waits on a workgroup that has not
+// started: a helper only waits for x blocks of the solver, which runs, and
+// the solver computes a far sum itself when no helper has taken that row.
+__global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
   const int nb = (a.m + 63) >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nfar = nb - 1 - kLA;  // block rows 0..nfar-1 take far sums from helpers
+  int* tick = a.ctl + 4 * (a.epoch & 1);
   __shared__ double red[kNW][64];
+  __shared__ int sticket;
+  if (threadIdx.x == 0) sticket = atomicAdd(tick, 1);
+  __syncthreads();
+  const int role = sticket;
+  __syncthreads();
 
-  if (blockIdx.x == 0) {
+  if (role == 0) {
     // ----------------------------- solver -----------------------------
+    // Near tiles of the current block row live in registers (tc, masked);
+    // those of the next block row and its diagonal tile are in flight (tx,
+    // dx) while the current block is solved, and are masked and staged after.
     __shared__ double ring[kRing][64];
     __shared__ int ringe[kRing];
-    __shared__ double tl[kLA][64 * kTLD];  // near tiles of the current block
-    __shared__ double dg[64 * kTLD];       // its diagonal block
-    __shared__ int sfE;
-    double tn[kLA][kCPW], dn[kCPW];
+    __shared__ double dgu[64 * kTLD];  // diagonal tile of the current block
+    __shared__ double dgs[64 * kTLD];  // the same with scaled columns
+    __shared__ int sfE, sEmax;
+    // the other ticket set belongs to the previous launch, which has ended;
+    // clear it for the next one
+    if (threadIdx.x < 4) a.ctl[4 * ((a.epoch + 1) & 1) + threadIdx.x] = 0;
+    double tc[kLA][kCPW], tx[kLA][kCPW], dx[kCPW];
     double facc = 0.0;
-    int fE = 0;
+    int fE = 0, emax = 0;
     uint64_t wlo = 0, whi = 0, wex = 0;  // pending far-sum words (wave 0)
-    // stage the first block's tiles
 #pragma unroll
-    for (int t = 0; t < kLA; ++t) load_tile(a, nb - 1, nb + t, false, lane, wave, tn[t]);
-    load_tile(a, nb - 1, nb - 1, true, lane, wave, dn);
-#pragma unroll
-    for (int t = 0; t < kLA; ++t)
-#pragma unroll
-      for (int q = 0; q < kCPW; ++q) tl[t][(wave * kCPW + q) * kTLD + lane] = tn[t][q];
-#pragma unroll
-    for (int q = 0; q < kCPW; ++q) dg[(wave * kCPW + q) * kTLD + lane] = dn[q];
-    __syncthreads();
+    for (int t = 0; t < kLA; ++t) {
+      load_tile(a, nb - 1, nb + t, lane, wave, tc[t]);
+      mask_tile(a, nb - 1, nb + t, false, lane, wave, tc[t]);
+    }
+    load_tile(a, nb - 1, nb - 1, lane, wave, dx);
+    mask_tile(a, nb - 1, nb - 1, true, lane, wave, dx);
+    stage_diag(dx, lane, wave, dgu, dgs);
     for (int ib = nb - 1; ib >= 0; --ib) {
       const int r0 = ib * 64;
       const int nr = min(64, a.m - r0);
@@ -183,10 +271,10 @@ __global__ __launch_bounds__(kNT) void k_trsv_la(TrsvArgs a) {
       const double crow = a.c[min(row, a.m - 1)];
       if (ib > 0) {
 #pragma unroll
-        for (int t = 0; t < kLA; ++t) load_tile(a, ib - 1, ib + t, false, lane, wave, tn[t]);
-        load_tile(a, ib - 1, ib - 1, true, lane, wave, dn);
+        for (int t = 0; t < kLA; ++t) load_tile(a, ib - 1, ib + t, lane, wave, tx[t]);
+        load_tile(a, ib - 1, ib - 1, lane, wave, dx);
       }
-      // near products: block columns ib+1 .. ib+kLA (tiles and x in LDS)
+      // near products: block columns ib+1 .. ib+kLA (x in LDS)
       int E = fE;
 #pragma unroll
       for (int t = 0; t < kLA; ++t)
@@ -197,10 +285,9 @@ __global__ __launch_bounds__(kNT) void k_trsv_la(TrsvArgs a) {
         const int cb = ib + 1 + t;
         if (cb < nb) {
           const double* xr = ring[cb % kRing] + wave * kCPW;
-          const double* tp = tl[t] + wave * kCPW * kTLD + lane;
           double s = 0.0;
 #pragma unroll
-          for (int q = 0; q < kCPW; ++q) s = fma(tp[q * kTLD], xr[q], s);
+          for (int q = 0; q < kCPW; ++q) s = fma(tc[t][q], xr[q], s);
           part = fma(s, ldexp(1.0, ringe[cb % kRing] - E), part);
         }
       }
@@ -213,7 +300,8 @@ __global__ __launch_bounds__(kNT) void k_trsv_la(TrsvArgs a) {
         for (int w = 0; w < kNW; ++w) tot += red[w][lane];
         const double rhs = live ? (ldexp(crow, -E) - tot - ldexp(facc, fE - E)) : 0.0;
         int e = E;
-        const double xo = diag_solve(rhs, dg, nr, lane, e);
+        const double xo = diag_solve(rhs, dgu, dgs, nr, lane, e);
+        emax = max(emax, e);
         ring[ib % kRing][lane] = xo;
         if (lane == 0) ringe[ib % kRing] = e;
         if (live) a.x[row] = xo;
@@ -221,85 +309,117 @@ __global__ __launch_bounds__(kNT) void k_trsv_la(TrsvArgs a) {
         publish_block(a.xll + (size_t)ib * kWords, a.epoch, xo, e, lane);
         // the far sum of the next block: complete the loads issued above
         if (want_far) {
+          const int rr = ib - 1;
+          const uint64_t* blk = a.all + (size_t)rr * kWords;
+          bool own = false;
           while (!__all(word_ok(wlo, a.epoch) && word_ok(whi, a.epoch) &&
                         word_ok(wex, a.epoch))) {
+            // not published yet: take the row if no helper has
+            const int handed = __hip_atomic_load(tick + 1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (handed <= nfar - 1 - rr) {
+              int got = 0;
+              if (lane == 0)
+                got = atomicCAS(tick + 1, nfar - 1 - rr, nfar - rr) == nfar - 1 - rr;
+              if (__shfl(got, 0, 64)) { own = true; break; }
+            }
             __builtin_amdgcn_s_sleep(1);
-            const uint64_t* blk = a.all + (size_t)(ib - 1) * kWords;
             wlo = ld_word(blk + 2 * lane);
             whi = ld_word(blk + 2 * lane + 1);
             wex = ld_word(blk + 128);
           }
-          facc = join_words(wlo, whi);
-          fE = (int)(uint32_t)wex;
+          if (own) {
+            facc = far_sum_wave(a, rr, nb, lane, fE);
+          } else {
+            facc = join_words(wlo, whi);
+            fE = (int)(uint32_t)wex;
+          }
         } else {
           facc = 0.0;
           fE = 0;
         }
         if (lane == 0) sfE = fE;
+        if (lane == 0) sEmax = emax;
       }
       __syncthreads();
       fE = sfE;  // every wave needs the far exponent; facc stays in wave 0
-      // stage the next block's tiles
+      // the next block's tiles: mask, keep the near ones, stage the diagonal
+      // (wave 0 read dgu/dgs before the barrier above; the barrier after the
+      // next near products orders these writes before its reads)
       if (ib > 0) {
 #pragma unroll
-        for (int t = 0; t < kLA; ++t)
+        for (int t = 0; t < kLA; ++t) {
+          mask_tile(a, ib - 1, ib + t, false, lane, wave, tx[t]);
 #pragma unroll
-          for (int q = 0; q < kCPW; ++q) tl[t][(wave * kCPW + q) * kTLD + lane] = tn[t][q];
-#pragma unroll
-        for (int q = 0; q < kCPW; ++q) dg[(wave * kCPW + q) * kTLD + lane] = dn[q];
+          for (int q = 0; q < kCPW; ++q) tc[t][q] = tx[t][q];
+        }
+        mask_tile(a, ib - 1, ib - 1, true, lane, wave, dx);
+        stage_diag(dx, lane, wave, dgu, dgs);
       }
-      __syncthreads();
     }
+    // bring every block to the largest exponent (entries smaller by more than
+    // the FP64 range become zero) and report it
+    __syncthreads();
+    const int Em = sEmax;
+    for (int i = threadIdx.x; i < a.m; i += kNT) {
+      const int d = a.exps[i >> 6] - Em;
+      if (d != 0) a.x[i] = ldexp(a.x[i], d);
+    }
+    if (threadIdx.x == 0) a.E_dev[0] = Em;
     return;
   }
 
   // ------------------------------ helpers ------------------------------
-  // Tiles and x words are double-buffered (A, B) so every load has two tile
-  // steps to arrive.  Each wavefront owns kCPW columns of every tile and reads
-  // their 2 kCPW words (lanes 0..2kCPW-1) and the exponent word (other lanes).
-  const int H = gridDim.x - 1;
-  const int h = blockIdx.x - 1;
-  const int widx = (lane < 2 * kCPW) ? (wave * 2 * kCPW + lane) : 128;
-  for (int r = nfar - 1 - h; r >= 0; r -= H) {
+  // A helper takes block rows r in decreasing order from the row ticket and,
+  // for each, streams the far tiles B(r, cb), cb = nb-1 down to r+kLA+1, as
+  // the solver publishes x_cb.  Tiles are double-buffered in registers (A, B).
+  // Wavefront 0 alone polls the published words of x_cb and copies the block
+  // into LDS; one barrier per tile hands it to the other wavefronts.
+  __shared__ double xs[2][64];
+  __shared__ int xe[2];
+  __shared__ int srow;
+  for (;;) {
+    if (threadIdx.x == 0) srow = atomicAdd(tick + 1, 1);
+    __syncthreads();
+    const int r = nfar - 1 - srow;
+    __syncthreads();
+    if (r < 0) break;
     double acc = 0.0;
     int E = 0;
     const int cend = r + 1 + kLA;  // last block column of the far part
     double tA[kCPW], tB[kCPW];
-    uint64_t wA, wB = 0;
-    load_tile(a, r, nb - 1, false, lane, wave, tA);
-    wA = ld_word(a.xll + (size_t)(nb - 1) * kWords + widx);
-    if (nb - 2 >= cend) {
-      load_tile(a, r, nb - 2, false, lane, wave, tB);
-      wB = ld_word(a.xll + (size_t)(nb - 2) * kWords + widx);
-    }
-    auto consume = [&](const double* t, uint64_t w, int cb) {
-      while (!__all(lane > 2 * kCPW || word_ok(w, a.epoch))) {
-        __builtin_amdgcn_s_sleep(1);
-        w = ld_word(a.xll + (size_t)cb * kWords + widx);
+    load_tile(a, r, nb - 1, lane, wave, tA);
+    if (nb - 2 >= cend) load_tile(a, r, nb - 2, lane, wave, tB);
+    auto consume = [&](double* t, int cb) {
+      if (wave == 0) {
+        const uint64_t* blk = a.xll + (size_t)cb * kWords;
+        uint64_t lo = ld_word(blk + 2 * lane), hi = ld_word(blk + 2 * lane + 1);
+        uint64_t ex = ld_word(blk + 128);
+        while (!__all(word_ok(lo, a.epoch) && word_ok(hi, a.epoch) && word_ok(ex, a.epoch))) {
+          __builtin_amdgcn_s_sleep(2);
+          lo = ld_word(blk + 2 * lane);
+          hi = ld_word(blk + 2 * lane + 1);
+          ex = ld_word(blk + 128);
+        }
+        xs[cb & 1][lane] = join_words(lo, hi);
+        if (lane == 0) xe[cb & 1] = (int)(uint32_t)ex;
       }
-      const int ec = (int)(uint32_t)__shfl(w, 2 * kCPW, 64);
+      __syncthreads();
+      mask_tile(a, r, cb, false, lane, wave, t);
+      const int ec = xe[cb & 1];
+      const double* xv = xs[cb & 1] + wave * kCPW;
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < kCPW; ++q) {
-        const uint64_t lo = __shfl(w, 2 * q, 64);
-        const uint64_t hi = __shfl(w, 2 * q + 1, 64);
-        s = fma(t[q], join_words(lo, hi), s);
-      }
+      for (int q = 0; q < kCPW; ++q) s = fma(t[q], xv[q], s);
       if (ec > E) { acc = ldexp(acc, E - ec); E = ec; }
       acc = fma(s, ldexp(1.0, ec - E), acc);
     };
     for (int cb = nb - 1; cb >= cend; cb -= 2) {
-      consume(tA, wA, cb);
-      if (cb - 2 >= cend) {
-        load_tile(a, r, cb - 2, false, lane, wave, tA);
-        wA = ld_word(a.xll + (size_t)(cb - 2) * kWords + widx);
-      }
+      consume(tA, cb);
+      if (cb - 2 >= cend) load_tile(a, r, cb - 2, lane, wave, tA);
       if (cb - 1 >= cend) {
-        consume(tB, wB, cb - 1);
-        if (cb - 3 >= cend) {
-          load_tile(a, r, cb - 3, false, lane, wave, tB);
-          wB = ld_word(a.xll + (size_t)(cb - 3) * kWords + widx);
-        }
+        consume(tB, cb - 1);
+        if (cb - 3 >= cend) load_tile(a, r, cb - 3, lane, wave, tB);
       }
     }
     // every wave saw the same exponents, so the partial sums share E
@@ -315,57 +435,25 @@ __global__ __launch_bounds__(kNT) void k_trsv_la(TrsvArgs a) {
   }
 }
 
-// Shift blocks to the largest exponent; E_dev = that exponent.
-__global__ __launch_bounds__(1024) void k_trsv_fin(int m, double* x, const int* exps, int* E_dev) {
-  __shared__ int smax[16];
-  const int nb = (m + 63) >> 6;
-  int e = 0;
-  for (int i = threadIdx.x; i < nb; i += 1024) e = max(e, exps[i]);
-  e = wave_max_i(e);
-  if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = e;
-  __syncthreads();
-  int E = 0;
-  for (int i = 0; i < 16; ++i) E = max(E, smax[i]);
-  for (int i = threadIdx.x; i < m; i += 1024) {
-    const int d = exps[i >> 6] - E;
-    if (d != 0) x[i] = ldexp(x[i], d);
-  }
-  if (threadIdx.x == 0) E_dev[0] = E;
-}
-
-static int trsv_grid_cap() {
-  static int cap = 0;
-  if (cap == 0) {
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_trsv_la, kNT, 0) != hipSuccess ||
-        per < 1)
-      per = 1;
-    cap = per * num_cus();
-  }
-  return cap;
-}
-
-// flags area layout: exps[nb] ints, then (256-aligned) xll[(nb+1) * kWords]
-// and all[(nb+1) * kWords] 64-bit words.
+// flags area layout: ctl[8] ints and exps[nb] ints, then (256-aligned)
+// xll[(nb+1) * kWords] and all[(nb+1) * kWords] 64-bit words.
 size_t trsv_flag_bytes(int m) {
   const size_t nb = (size_t)(m + 63) / 64 + 1;
-  return 256 + nb * sizeof(int) + 256 + 2 * nb * kWords * sizeof(uint64_t) + 256;
+  return 256 + (8 + nb) * sizeof(int) + 256 + 2 * nb * kWords * sizeof(uint64_t) + 256;
 }
 
 void trsv_upper_scaled(hipStream_t st, int m, const double* B, int ldb, const double* c,
-                       double* x, int* flags, int epoch, int* E_dev) {
+                       double* x, int* flags, int epoch, int* E_dev, bool solo) {
   if (m <= 0) return;
   const int nb = (m + 63) / 64;
-  int* exps = flags;
-  uint64_t* xll = (uint64_t*)(((uintptr_t)(flags + nb + 1) + 255) & ~(uintptr_t)255);
+  int* ctl = flags;
+  int* exps = flags + 8;
+  uint64_t* xll = (uint64_t*)(((uintptr_t)(exps + nb + 1) + 255) & ~(uintptr_t)255);
   uint64_t* all = xll + (size_t)(nb + 1) * kWords;
   const int nfar = nb - 1 - kLA;
-  const int helpers = nfar > 0 ? std::min(nfar, trsv_grid_cap() - 1) : 0;
-  TrsvArgs args{m, B, ldb, c, x, exps, xll, all, (uint32_t)epoch};
-  void* kargs[] = {(void*)&args};
-  (void)hipLaunchCooperativeKernel((const void*)k_trsv_la, dim3(1 + helpers), dim3(kNT), kargs,
-                                   0, st);
-  hipLaunchKernelGGL(k_trsv_fin, dim3(1), dim3(1024), 0, st, m, x, exps, E_dev);
+  const int helpers = (nfar > 0 && !solo) ? std::min(nfar, num_cus() - 1) : 0;
+  TrsvArgs args{m, B, ldb, c, x, exps, xll, all, ctl, E_dev, (uint32_t)epoch};
+  hipLaunchKernelGGL(k_trsv, dim3(1 + helpers), dim3(kNT), 0, st, args);
 }
 
 }  // namespace htk

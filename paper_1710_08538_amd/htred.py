@@ -18,6 +18,7 @@ HT_QZ_IDENTITY, HT_QZ_ACCUMULATE, HT_QZ_NONE = 0, 1, 2
 HT_PREC_FP64, HT_PREC_SPLIT_BF16, HT_PREC_SPLIT_FP8 = 0, 1, 2
 HT_FLAG_CHECK_FINITE = 1
 HT_FLAG_PROFILE = 2
+HT_FLAG_SOLVE_SOLO = 4
 PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain", "sweep")
 
 
@@ -125,12 +126,13 @@ def _check(rc):
 
 def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
            prec=HT_PREC_FP64, stats=False, workspace=None, stream=None, check_finite=False,
-           profile=False):
+           profile=False, solve_solo=False):
     """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
 
     A, B: n x n column-major float64 GPU tensors (B upper triangular).
     Q, Z: optional preallocated outputs (allocated when None).
     workspace: optional uint8 GPU tensor of >= workspace_size(n) bytes.
+    solve_solo: run every triangular solve on one workgroup (testing).
     """
     n = A.shape[0]
     lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
@@ -141,7 +143,8 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     ldq, ldz = _ld(Q, n, "Q"), _ld(Z, n, "Z")
     o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
                 flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
-                | (HT_FLAG_PROFILE if profile else 0))
+                | (HT_FLAG_PROFILE if profile else 0)
+                | (HT_FLAG_SOLVE_SOLO if solve_solo else 0))
     st = Stats()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
