@@ -1,20 +1,19 @@
 // ht_trsv.hip -- overflow-safe upper triangular solve B x = 2^{-E} c behind
 // the opposite reflectors (Sec. 2.2, step c of Sec. 3.2.2).
 //
-// Rows are split into 64-row blocks.  One "solver" workgroup walks the blocks
-// bottom-up and performs the substitution: for block i it adds the products
-// of the kLA block columns right of the diagonal (tiles prefetched one step
-// ahead and staged in LDS, x of those blocks kept in LDS), takes the sum over
-// all farther block columns from a helper, and runs the 64-row back
-// substitution of the diagonal block on one wavefront.  Every other
-// workgroup is a helper that owns block rows and streams their far tiles
-// B(i, c), c >= i+kLA+1, as the solver publishes x_c, then publishes the far
-// sum of block i ahead of the solver's arrival.  The launch is cooperative,
-// so every workgroup is resident and the spin-waits terminate.
-//
-// Workgroups have 1024 threads (16 wavefronts); a 64 x 64 tile is read with
-// lanes on consecutive rows (512 contiguous bytes per column) and 4 columns
-// per wavefront, so a thread has only 4 loads in flight per tile.
+// Rows are split into 64-row blocks, solved bottom-up.  For block b,
+//   x_b = B_bb^{-1} (c_b - B_{b,b+1} x_{b+1} - [B_{b,b+2} x_{b+2} + B_{b,b+3} x_{b+3}]
+//                       - sum_{c >= b+4} B_{b,c} x_c),
+// and the four parts are produced by different hands, so that the serial
+// substitution is the only work on the critical path:
+//   * the substitution of block b+1 (one wavefront) also accumulates
+//     B_{b,b+1} x_{b+1}, one extra FMA per row off its dependency chain;
+//   * the other fifteen wavefronts of the solver workgroup ("staff") compute
+//     B_{b,b+2} x_{b+2} + B_{b,b+3} x_{b+3} and stage the next diagonal and
+//     coupling tiles in LDS while that substitution runs;
+//   * helper workgroups stream the far tiles of a block row as the x blocks
+//     are published and publish its far sum long before it is needed.
+// The solver workgroup synchronises once per block.
 //
 // Publication uses 64-bit words that carry the call's epoch in the upper
 // half and 32 data bits in the lower half (a double takes two words).  A
@@ -22,11 +21,13 @@
 // in every word of a block has the whole block: one round trip, no fences.
 //
 // Scaling: the solution of a triangular system with a small diagonal grows
-// geometrically and overflows FP64 (the ill-conditioned test pencils reach
-// 1e+300 within a few hundred rows).  Every block carries its own
-// power-of-two exponent e_i (true value = x_i 2^{e_i}); sums align exponents
-// to their largest term, and the substitution inside a block rescales by
-// 2^-600 whenever an entry would exceed 2^600 times its pivot.  The final
+// geometrically and overflows FP64 (ill-conditioned pencils reach 1e+300
+// within a few hundred rows).  Every block carries its own power-of-two
+// exponent e_b (true value = x_b 2^{e_b}); sums align exponents to their
+// largest term.  The substitution works in 8-row chunks: after a chunk, if
+// an entry of x exceeds 2^300 everything is scaled by 2^-600, and if one
+// exceeds 2^600 (or is not finite) the chunk is redone row by row, scaling
+// by 2^-600 before any entry would exceed 2^600 times its pivot.  The final
 // pass shifts all blocks to the largest exponent E (entries smaller by more
 // than the FP64 range become zero) and reports E: only the direction of x
 // enters an opposite reflector (Lemma 2.1).
@@ -35,13 +36,15 @@
 
 namespace htk {
 
-constexpr int kLA = 3;       // near block columns handled by the solver
+constexpr int kLA = 3;       // near block columns handled inside the solver workgroup
 constexpr int kRing = 4;     // x blocks kept in LDS (>= kLA + 1)
 constexpr int kWords = 130;  // per block: 128 words for 64 doubles + exponent + pad
 constexpr int kNT = 1024;    // threads per workgroup
 constexpr int kNW = kNT / 64;
-constexpr int kCPW = 64 / kNW;  // tile columns per wavefront
-constexpr int kTLD = 65;     // LDS leading dimension of a staged tile
+constexpr int kCPW = 64 / kNW;  // helper tile columns per wavefront
+constexpr int kSW = kNW - 1;    // staff wavefronts of the solver workgroup
+constexpr int kSC = 5;          // staff tile columns per wavefront: (wave - 1) + 15 k
+constexpr double kWarn = 0x1.0p300;
 
 struct TrsvArgs {
   int m;
@@ -78,11 +81,10 @@ __device__ __forceinline__ void publish_block(uint64_t* blk, uint32_t epoch, dou
   if (lane == 0) st_word(blk + 128, epoch, (uint32_t)e);
 }
 
-// This thread's part of tile B(block row ib, block column cb):
-// t[q] = B(64 ib + lane, 64 cb + kCPW wave + q).  Addresses are clamped into
-// the matrix and the loads carry no condition, so they all issue back to
-// back; the entries outside the matrix (and below the diagonal of a diagonal
-// tile) are zeroed by mask_tile when the values are used.
+// Helper tiles: t[q] = B(64 ib + lane, 64 cb + kCPW wave + q).  Addresses are
+// clamped into the matrix and the loads carry no condition, so they all issue
+// back to back; entries outside the matrix are zeroed by mask_tile when the
+// values are used.
 __device__ __forceinline__ void load_tile(const TrsvArgs& a, int ib, int cb, int lane, int wave,
                                           double t[kCPW]) {
   const int rowc = min(ib * 64 + lane, a.m - 1);
@@ -93,100 +95,38 @@ __device__ __forceinline__ void load_tile(const TrsvArgs& a, int ib, int cb, int
     t[q] = a.B[(size_t)rowc + (size_t)colc * a.ldb];
   }
 }
-__device__ __forceinline__ void mask_tile(const TrsvArgs& a, int ib, int cb, bool diag, int lane,
-                                          int wave, double t[kCPW]) {
+__device__ __forceinline__ void mask_tile(const TrsvArgs& a, int ib, int cb, int lane, int wave,
+                                          double t[kCPW]) {
   const int row = ib * 64 + lane;
   const int cbase = cb * 64 + wave * kCPW;
 #pragma unroll
   for (int q = 0; q < kCPW; ++q) {
-    const int col = cbase + q;
-    const bool ok = row < a.m && col < a.m && cb >= 0 && (!diag || col >= row);
+    const bool ok = row < a.m && cbase + q < a.m && cb >= 0;
     t[q] = ok ? t[q] : 0.0;
   }
 }
 
-// Stage a masked diagonal tile in LDS twice: dgu as is, dgs with column c
-// divided by its pivot and the pivot itself replaced by 0, so that the fast
-// substitution needs one FMA per row.  Rows beyond the matrix get pivot 1
-// and no coupling.  A zero pivot survives only when ||B||_F = 0; any
-// direction then works, and it is treated as 1.
-__device__ __forceinline__ void stage_diag(const double t[kCPW], int lane, int wave, double* dgu,
-                                           double* dgs) {
-  // the wavefront's kCPW pivots, gathered into lanes 0..kCPW-1 so that one
-  // division serves them all
-  double piv = 1.0;
+// Staff tiles: t[k] = B(64 rb + lane, 64 cb + (wv-1) + 15 k) for the columns
+// that exist (zero otherwise; rows beyond the matrix hold a clamped copy and
+// are masked by the user).  The column address is uniform (scalar), the row
+// offset is the lane.
+__device__ __forceinline__ void staff_load(const TrsvArgs& a, int nb, int rb, int cb, int wv,
+                                           int lane, double t[kSC]) {
+  if (rb < 0 || rb >= nb || cb < 0 || cb >= nb) {
 #pragma unroll
-  for (int q = 0; q < kCPW; ++q) {
-    const double d = readlane_d(t[q], wave * kCPW + q);
-    if (lane == q) piv = d;
+    for (int k = 0; k < kSC; ++k) t[k] = 0.0;
+    return;
   }
-  const double inv = (piv != 0.0) ? 1.0 / piv : 1.0;
+  const int roff = min(lane, a.m - 1 - 64 * rb);
 #pragma unroll
-  for (int q = 0; q < kCPW; ++q) {
-    const int c = wave * kCPW + q;
-    const double dinv = readlane_d(inv, q);
-    dgu[c * kTLD + lane] = t[q];
-    dgs[c * kTLD + lane] = (lane < c) ? t[q] * dinv : 0.0;
+  for (int k = 0; k < kSC; ++k) {
+    const int cc = (wv - 1) + 15 * k;
+    const int col = 64 * cb + cc;
+    if (cc < 64 && col < a.m)
+      t[k] = a.B[(size_t)col * a.ldb + (size_t)(64 * rb) + roff];
+    else
+      t[k] = 0.0;
   }
-}
-
-// Back substitution of one 64-row diagonal block on one wavefront: lane l
-// holds row l of the right-hand side (rows >= nr hold zeros).  Returns the
-// lane's entry of x and updates the block exponent e.  The fast pass runs
-// rhs_i -= (B_ir / B_rr) rhs_r down the rows and divides at the end; if any
-// entry of the result exceeds 2^600 or is not finite, the block is redone
-// from the unscaled tile with a per-row rescaling by 2^-600.
-__device__ __forceinline__ double diag_solve(double rhs0, const double* dgu, const double* dgs,
-                                             int nr, int lane, int& e) {
-  const bool live = lane < nr;
-  const double d_own = live ? dgu[lane * kTLD + lane] : 1.0;
-  const double dinv = (d_own != 0.0) ? 1.0 / d_own : 1.0;
-  // The scaled couplings are read from LDS 8 rows at a time, one chunk
-  // ahead of the substitution (the empty asm statements keep the compiler
-  // from sinking the reads next to their uses), so the dependency chain per
-  // row is a readlane and an FMA.  Row 0 has no coupling (its column is 0).
-  double rhs = rhs0;
-  double ca[8], cb[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) ca[i] = dgs[(63 - i) * kTLD + lane];
-#pragma unroll
-  for (int ch = 0; ch < 8; ++ch) {
-    const int rtop = 63 - 8 * ch;
-    __asm__ volatile("" ::: "memory");
-    if (ch + 1 < 8) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) cb[i] = dgs[(rtop - 8 - i) * kTLD + lane];
-    }
-    __asm__ volatile("" ::: "memory");
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (rtop - i >= 1) rhs = fma(-ca[i], readlane_d(rhs, rtop - i), rhs);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) ca[i] = cb[i];
-  }
-  const double xf = rhs * dinv;
-  const bool bad = live && !(fabs(xf) <= kBig);
-  if (!__any(bad)) return live ? xf : 0.0;
-  // careful pass
-  rhs = rhs0;
-  double xo = 0.0;
-  for (int r = nr - 1; r >= 0; --r) {
-    double t = readlane_d(rhs, r);
-    const double dr0 = readlane_d(d_own, r);
-    const double dr = (dr0 != 0.0) ? dr0 : 1.0;
-    int guard = 0;
-    while (!(fabs(t) <= kBig * fabs(dr)) && guard < 8) {
-      rhs *= kShrink;
-      xo *= kShrink;
-      e += kShrinkExp;
-      t = readlane_d(rhs, r);
-      ++guard;
-    }
-    const double xr = t * readlane_d(dinv, r);
-    if (lane == r) xo = xr;
-    rhs = fma(-dgu[r * kTLD + lane], xr, rhs);
-  }
-  return live ? xo : 0.0;
 }
 
 // Far sum of block row r, sum over block columns cb >= r+kLA+1 of
@@ -214,6 +154,160 @@ __device__ double far_sum_wave(const TrsvArgs& a, int r, int nb, int lane, int& 
   return acc;
 }
 
+// LDS of the solver workgroup.  Staged tiles are column-major with leading
+// dimension 64: gs = diagonal tile with column c divided by its pivot and
+// zero on and below the diagonal, ts = coupling tile B(b-1, b) divided the
+// same way; pv = pivots (1 where zero or beyond the matrix), iv = 1 / pv.
+struct SolverLds {
+  double gs[2][64 * 64];
+  double ts[2][64 * 64];
+  double pv[2][64];
+  double iv[2][64];
+  double part[2][kSW][64];  // staff partial products for the next block
+  double ring[kRing][64];   // recent x blocks
+  int ringe[kRing];
+  int bad[2][kSW];          // a staged scaled entry is not finite
+  int emax;
+};
+
+// Stage block blk's tiles into buffer `buf` (staff wavefront wv, columns
+// (wv-1) + 15 k): dg holds rows of block blk, dt rows of block blk-1.
+__device__ __forceinline__ void staff_stage(const TrsvArgs& a, SolverLds& L, int buf, int blk,
+                                            const double dg[kSC], const double dt[kSC], int wv,
+                                            int lane) {
+  // the wavefront's pivots gathered into lanes 0..kSC-1: one division
+  double psel = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSC; ++k) {
+    const int cc = (wv - 1) + 15 * k;
+    if (cc < 64) {
+      const double d = readlane_d(dg[k], cc);
+      if (lane == k) psel = d;
+    }
+  }
+  const double inv = (psel != 0.0) ? 1.0 / psel : 1.0;
+  const bool rowok = 64 * blk + lane < a.m;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < kSC; ++k) {
+    const int cc = (wv - 1) + 15 * k;
+    if (cc < 64) {
+      const double ik = readlane_d(inv, k);
+      const double pk = readlane_d(psel, k);
+      const double g = (rowok && lane < cc) ? dg[k] * ik : 0.0;
+      const double t = (blk >= 1) ? dt[k] * ik : 0.0;
+      L.gs[buf][cc * 64 + lane] = g;
+      L.ts[buf][cc * 64 + lane] = t;
+      if (lane == 0) {
+        L.iv[buf][cc] = ik;
+        L.pv[buf][cc] = (pk != 0.0) ? pk : 1.0;
+      }
+      bad = bad || !(fabs(g) <= __DBL_MAX__) || !(fabs(t) <= __DBL_MAX__);
+    }
+  }
+  const bool anybad = __any(bad);
+  if (lane == 0) L.bad[buf][wv - 1] = anybad ? 1 : 0;
+}
+
+// Substitution of block b on wavefront 0.  In: rhs (lane l = row l, zero
+// beyond the matrix) at exponent e.  Out: rhs holds the substituted values y
+// (x = y / pivot), r2 the coupling sum B(b-1, b) x_b, both at the returned
+// exponent e.
+__device__ __forceinline__ void wave0_substitute(const SolverLds& L, int buf, int lane,
+                                                 double& rhs, double& r2, int& e) {
+  const double* gs = L.gs[buf];
+  const double* ts = L.ts[buf];
+  const double dinv = L.iv[buf][lane];
+  const double dp = L.pv[buf][lane];
+  double ga[8], ta[8], gb[8], tb[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    ga[i] = gs[(63 - i) * 64 + lane];
+    ta[i] = ts[(63 - i) * 64 + lane];
+  }
+  r2 = 0.0;
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    const int rtop = 63 - 8 * ch;
+    __asm__ volatile("" ::: "memory");
+    if (ch + 1 < 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        gb[i] = gs[(rtop - 8 - i) * 64 + lane];
+        tb[i] = ts[(rtop - 8 - i) * 64 + lane];
+      }
+    }
+    __asm__ volatile("" ::: "memory");
+    const double rs = rhs, rs2 = r2;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double y = readlane_d(rhs, rtop - i);
+      rhs = fma(-ga[i], y, rhs);
+      r2 = fma(ta[i], y, r2);
+    }
+    const double xv = fabs(rhs * dinv);
+    const bool inch = lane <= rtop && lane > rtop - 8;
+    if (__any(inch && !(xv <= kBig))) {
+      // redo the chunk row by row with scaling before each division
+      rhs = rs;
+      r2 = rs2;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int r = rtop - i;
+        double t = readlane_d(rhs, r);
+        const double dr = readlane_d(dp, r);
+        int guard = 0;
+        while (!(fabs(t) <= kBig * fabs(dr)) && guard < 8) {
+          rhs *= kShrink;
+          r2 *= kShrink;
+          e += kShrinkExp;
+          t = readlane_d(rhs, r);
+          ++guard;
+        }
+        rhs = fma(-ga[i], t, rhs);
+        r2 = fma(ta[i], t, r2);
+      }
+    } else if (__any(inch && xv > kWarn)) {
+      rhs *= kShrink;
+      r2 *= kShrink;
+      e += kShrinkExp;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      ga[i] = gb[i];
+      ta[i] = tb[i];
+    }
+  }
+}
+
+// The same from the unscaled matrix in global memory, row by row; used when
+// a scaled entry of the staged tiles is not finite (a pivot tiny relative to
+// its column).
+__device__ void wave0_substitute_slow(const TrsvArgs& a, const SolverLds& L, int buf, int b,
+                                      int nr, int lane, double& rhs, double& r2, int& e) {
+  const double dinv = L.iv[buf][lane];
+  const double dp = L.pv[buf][lane];
+  r2 = 0.0;
+  for (int r = nr - 1; r >= 0; --r) {
+    double t = readlane_d(rhs, r);
+    const double dr = readlane_d(dp, r);
+    int guard = 0;
+    while (!(fabs(t) <= kBig * fabs(dr)) && guard < 8) {
+      rhs *= kShrink;
+      r2 *= kShrink;
+      e += kShrinkExp;
+      t = readlane_d(rhs, r);
+      ++guard;
+    }
+    const double xr = t * readlane_d(dinv, r);
+    const double* col = a.B + (size_t)(64 * b + r) * a.ldb;
+    const double own = (lane < r) ? col[64 * b + lane] : 0.0;
+    const double up = (b >= 1) ? col[64 * (b - 1) + lane] : 0.0;
+    rhs = fma(-own, xr, rhs);
+    r2 = fma(up, xr, r2);
+  }
+}
+
 // One launch solves the system.  The first workgroup to start takes the
 // solver role (a ticket from ctl), the others are helpers that take block
 // rows from a second ticket.  Nothing waits on a workgroup that has not
@@ -221,7 +315,8 @@ __device__ double far_sum_wave(const TrsvArgs& a, int r, int nb, int lane, int& 
 // the solver computes a far sum itself when no helper has taken that row.
 __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
   const int nb = (a.m + 63) >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nfar = nb - 1 - kLA;  // block rows 0..nfar-1 take far sums from helpers
   int* tick = a.ctl + 4 * (a.epoch & 1);
   __shared__ double red[kNW][64];
@@ -233,83 +328,61 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
 
   if (role == 0) {
     // ----------------------------- solver -----------------------------
-    // Near tiles of the current block row live in registers (tc, masked);
-    // those of the next block row and its diagonal tile are in flight (tx,
-    // dx) while the current block is solved, and are masked and staged after.
-    __shared__ double ring[kRing][64];
-    __shared__ int ringe[kRing];
-    __shared__ double dgu[64 * kTLD];  // diagonal tile of the current block
-    __shared__ double dgs[64 * kTLD];  // the same with scaled columns
-    __shared__ int sfE, sEmax;
+    __shared__ SolverLds L;
     // the other ticket set belongs to the previous launch, which has ended;
     // clear it for the next one
     if (threadIdx.x < 4) a.ctl[4 * ((a.epoch + 1) & 1) + threadIdx.x] = 0;
-    double tc[kLA][kCPW], tx[kLA][kCPW], dx[kCPW];
-    double facc = 0.0;
-    int fE = 0, emax = 0;
-    uint64_t wlo = 0, whi = 0, wex = 0;  // pending far-sum words (wave 0)
-#pragma unroll
-    for (int t = 0; t < kLA; ++t) {
-      load_tile(a, nb - 1, nb + t, lane, wave, tc[t]);
-      mask_tile(a, nb - 1, nb + t, false, lane, wave, tc[t]);
-    }
-    load_tile(a, nb - 1, nb - 1, lane, wave, dx);
-    mask_tile(a, nb - 1, nb - 1, true, lane, wave, dx);
-    stage_diag(dx, lane, wave, dgu, dgs);
-    for (int ib = nb - 1; ib >= 0; --ib) {
-      const int r0 = ib * 64;
-      const int nr = min(64, a.m - r0);
-      const int row = r0 + lane;
-      const bool want_far = (ib - 1 >= 0) && (ib - 1 < nfar);
-      // issue the loads of the next block's far sum and tiles (used next step)
-      if (wave == 0 && want_far) {
-        const uint64_t* blk = a.all + (size_t)(ib - 1) * kWords;
-        wlo = ld_word(blk + 2 * lane);
-        whi = ld_word(blk + 2 * lane + 1);
-        wex = ld_word(blk + 128);
-      }
-      const double crow = a.c[min(row, a.m - 1)];
-      if (ib > 0) {
-#pragma unroll
-        for (int t = 0; t < kLA; ++t) load_tile(a, ib - 1, ib + t, lane, wave, tx[t]);
-        load_tile(a, ib - 1, ib - 1, lane, wave, dx);
-      }
-      // near products: block columns ib+1 .. ib+kLA (x in LDS)
-      int E = fE;
-#pragma unroll
-      for (int t = 0; t < kLA; ++t)
-        if (ib + 1 + t < nb) E = max(E, ringe[(ib + 1 + t) % kRing]);
-      double part = 0.0;
-#pragma unroll
-      for (int t = 0; t < kLA; ++t) {
-        const int cb = ib + 1 + t;
-        if (cb < nb) {
-          const double* xr = ring[cb % kRing] + wave * kCPW;
-          double s = 0.0;
-#pragma unroll
-          for (int q = 0; q < kCPW; ++q) s = fma(tc[t][q], xr[q], s);
-          part = fma(s, ldexp(1.0, ringe[cb % kRing] - E), part);
-        }
-      }
-      red[wave][lane] = part;
-      __syncthreads();
-      if (wave == 0) {
+    if (wave == 0) {
+      // ---- substitution wavefront ----
+      double rhs2 = 0.0, facc = 0.0, crow;
+      int e2 = 0, fE = 0, emax = 0;
+      crow = a.c[min(64 * (nb - 1) + lane, a.m - 1)];
+      __syncthreads();  // staged tiles of block nb-1
+      for (int b = nb - 1; b >= 0; --b) {
+        const int buf = b & 1;
+        const int nr = min(64, a.m - 64 * b);
         const bool live = lane < nr;
-        double tot = 0.0;
+        const bool want_far = (b - 1 >= 0) && (b - 1 < nfar);
+        uint64_t wlo = 0, whi = 0, wex = 0;
+        if (want_far) {
+          const uint64_t* blk = a.all + (size_t)(b - 1) * kWords;
+          wlo = ld_word(blk + 2 * lane);
+          whi = ld_word(blk + 2 * lane + 1);
+          wex = ld_word(blk + 128);
+        }
+        // right-hand side at a common exponent
+        int eP = 0;
+        double sumP = 0.0;
+        if (b + 2 < nb) {
+          eP = L.ringe[(b + 2) % kRing];
+          if (b + 3 < nb) eP = max(eP, L.ringe[(b + 3) % kRing]);
 #pragma unroll
-        for (int w = 0; w < kNW; ++w) tot += red[w][lane];
-        const double rhs = live ? (ldexp(crow, -E) - tot - ldexp(facc, fE - E)) : 0.0;
+          for (int w = 0; w < kSW; ++w) sumP += L.part[buf][w][lane];
+        }
+        const int E = max(max(e2, eP), fE);
+        double rhs = live ? (ldexp(crow, -E) - ldexp(rhs2, e2 - E) - ldexp(sumP, eP - E) -
+                             ldexp(facc, fE - E))
+                          : 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int w = 0; w < kSW; ++w) bad |= L.bad[buf][w];
         int e = E;
-        const double xo = diag_solve(rhs, dgu, dgs, nr, lane, e);
+        double r2;
+        if (!bad) wave0_substitute(L, buf, lane, rhs, r2, e);
+        else wave0_substitute_slow(a, L, buf, b, nr, lane, rhs, r2, e);
+        const double xo = live ? rhs * L.iv[buf][lane] : 0.0;
         emax = max(emax, e);
-        ring[ib % kRing][lane] = xo;
-        if (lane == 0) ringe[ib % kRing] = e;
-        if (live) a.x[row] = xo;
-        if (lane == 0) a.exps[ib] = e;
-        publish_block(a.xll + (size_t)ib * kWords, a.epoch, xo, e, lane);
+        L.ring[b % kRing][lane] = xo;
+        if (lane == 0) L.ringe[b % kRing] = e;
+        if (live) a.x[64 * b + lane] = xo;
+        if (lane == 0) a.exps[b] = e;
+        publish_block(a.xll + (size_t)b * kWords, a.epoch, xo, e, lane);
+        rhs2 = r2;
+        e2 = e;
+        if (b >= 1) crow = a.c[64 * (b - 1) + lane];
         // the far sum of the next block: complete the loads issued above
         if (want_far) {
-          const int rr = ib - 1;
+          const int rr = b - 1;
           const uint64_t* blk = a.all + (size_t)rr * kWords;
           bool own = false;
           while (!__all(word_ok(wlo, a.epoch) && word_ok(whi, a.epoch) &&
@@ -338,29 +411,75 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
           facc = 0.0;
           fE = 0;
         }
-        if (lane == 0) sfE = fE;
-        if (lane == 0) sEmax = emax;
+        __syncthreads();
+      }
+      if (lane == 0) L.emax = emax;
+    } else {
+      // ---- staff wavefronts ----
+      // Tile sets: for the step that solves block s they hold
+      // p1 = B(s-1, s+1), p2 = B(s-1, s+2), dg = B(s-1, s-1), dt = B(s-2, s-1),
+      // loaded two steps ahead (set X for blocks nb-1, nb-3, ..., Y for the others).
+      double xp1[kSC], xp2[kSC], xdg[kSC], xdt[kSC];
+      double yp1[kSC], yp2[kSC], ydg[kSC], ydt[kSC];
+      {
+        double dg0[kSC], dt0[kSC];
+        staff_load(a, nb, nb - 1, nb - 1, wave, lane, dg0);
+        staff_load(a, nb, nb - 2, nb - 1, wave, lane, dt0);
+        const int s = nb - 1;
+        staff_load(a, nb, s - 1, s + 1, wave, lane, xp1);
+        staff_load(a, nb, s - 1, s + 2, wave, lane, xp2);
+        staff_load(a, nb, s - 1, s - 1, wave, lane, xdg);
+        staff_load(a, nb, s - 2, s - 1, wave, lane, xdt);
+        const int s2 = nb - 2;
+        staff_load(a, nb, s2 - 1, s2 + 1, wave, lane, yp1);
+        staff_load(a, nb, s2 - 1, s2 + 2, wave, lane, yp2);
+        staff_load(a, nb, s2 - 1, s2 - 1, wave, lane, ydg);
+        staff_load(a, nb, s2 - 2, s2 - 1, wave, lane, ydt);
+        staff_stage(a, L, (nb - 1) & 1, nb - 1, dg0, dt0, wave, lane);
       }
       __syncthreads();
-      fE = sfE;  // every wave needs the far exponent; facc stays in wave 0
-      // the next block's tiles: mask, keep the near ones, stage the diagonal
-      // (wave 0 read dgu/dgs before the barrier above; the barrier after the
-      // next near products orders these writes before its reads)
-      if (ib > 0) {
+      auto step = [&](int b, double* p1, double* p2, double* dg, double* dt)
+                      __attribute__((always_inline)) {
+        if (b - 1 >= 0) {
+          // partial products of block b-1 with x_{b+1}, x_{b+2}
+          int e1 = 0, ex2 = 0;
+          if (b + 1 < nb) e1 = L.ringe[(b + 1) % kRing];
+          if (b + 2 < nb) ex2 = L.ringe[(b + 2) % kRing];
+          const int eP = (b + 2 < nb) ? max(e1, ex2) : e1;
+          double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-        for (int t = 0; t < kLA; ++t) {
-          mask_tile(a, ib - 1, ib + t, false, lane, wave, tx[t]);
-#pragma unroll
-          for (int q = 0; q < kCPW; ++q) tc[t][q] = tx[t][q];
+          for (int k = 0; k < kSC; ++k) {
+            const int cc = (wave - 1) + 15 * k;
+            if (cc < 64) {
+              if (b + 1 < nb) s1 = fma(p1[k], L.ring[(b + 1) % kRing][cc], s1);
+              if (b + 2 < nb) s2 = fma(p2[k], L.ring[(b + 2) % kRing][cc], s2);
+            }
+          }
+          double part = 0.0;
+          if (b + 1 < nb) part += ldexp(s1, e1 - eP);
+          if (b + 2 < nb) part += ldexp(s2, ex2 - eP);
+          L.part[(b - 1) & 1][wave - 1][lane] = part;
+          staff_stage(a, L, (b - 1) & 1, b - 1, dg, dt, wave, lane);
         }
-        mask_tile(a, ib - 1, ib - 1, true, lane, wave, dx);
-        stage_diag(dx, lane, wave, dgu, dgs);
+        // tiles for the step that solves block b-2
+        const int s = b - 2;
+        if (s >= 0) {
+          staff_load(a, nb, s - 1, s + 1, wave, lane, p1);
+          staff_load(a, nb, s - 1, s + 2, wave, lane, p2);
+          staff_load(a, nb, s - 1, s - 1, wave, lane, dg);
+          staff_load(a, nb, s - 2, s - 1, wave, lane, dt);
+        }
+        __syncthreads();
+      };
+      for (int b = nb - 1; b >= 0; b -= 2) {
+        step(b, xp1, xp2, xdg, xdt);
+        if (b - 1 >= 0) step(b - 1, yp1, yp2, ydg, ydt);
       }
     }
     // bring every block to the largest exponent (entries smaller by more than
     // the FP64 range become zero) and report it
     __syncthreads();
-    const int Em = sEmax;
+    const int Em = L.emax;
     for (int i = threadIdx.x; i < a.m; i += kNT) {
       const int d = a.exps[i >> 6] - Em;
       if (d != 0) a.x[i] = ldexp(a.x[i], d);
@@ -405,7 +524,7 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
         if (lane == 0) xe[cb & 1] = (int)(uint32_t)ex;
       }
       __syncthreads();
-      mask_tile(a, r, cb, false, lane, wave, t);
+      mask_tile(a, r, cb, lane, wave, t);
       const int ec = xe[cb & 1];
       const double* xv = xs[cb & 1] + wave * kCPW;
       double s = 0.0;
