@@ -316,25 +316,45 @@ void scale_pow2(hipStream_t st, double* x, int m, const int* e_dev, int sign) {
   if (m > 0) hipLaunchKernelGGL(k_scale_pow2, dim3(cdiv(m, 256)), dim3(256), 0, st, x, m, e_dev, sign);
 }
 
-// Frobenius norm: per-column-chunk scaled sums of squares, then a final pass.
+// Frobenius norm: per column, the sum of squares of the entries scaled by
+// an exact power of two that brings the column's largest magnitude into
+// [2^-450, 2^450] (no underflow of tiny columns, no overflow of huge ones);
+// the final pass brings the columns to the scale of the largest one.
 __global__ __launch_bounds__(256) void k_fro_part(int m, int n, const double* X, int ld,
                                                   double* part) {
   __shared__ double sh[4];
   const int j = blockIdx.x;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs(X[(size_t)i + (size_t)j * ld]));
+  mx = block_max(mx, sh);
+  const double sc = safe_scale(mx);
   double s = 0.0;
   for (int i = threadIdx.x; i < m; i += 256) {
-    double v = X[(size_t)i + (size_t)j * ld];
+    const double v = X[(size_t)i + (size_t)j * ld] * sc;
     s = fma(v, v, s);
   }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) part[j] = s;
+  if (threadIdx.x == 0) {
+    part[j] = s;
+    part[n + j] = sc;
+  }
 }
 __global__ __launch_bounds__(256) void k_fro_fin(int n, const double* part, double* out) {
   __shared__ double sh[4];
+  // the smallest column scale belongs to the largest column (scales are
+  // powers of two, so their reciprocals are exact)
+  double imax = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256)
+    if (part[j] > 0.0) imax = fmax(imax, 1.0 / part[n + j]);
+  imax = block_max(imax, sh);
+  const double smin = (imax > 0.0) ? 1.0 / imax : 1.0;
   double s = 0.0;
-  for (int j = threadIdx.x; j < n; j += 256) s += part[j];
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double r = smin / part[n + j];  // power of two <= 1
+    s = fma(part[j] * r, r, s);
+  }
   s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[0] = sqrt(s);
+  if (threadIdx.x == 0) out[0] = (s > 0.0) ? sqrt(s) / smin : 0.0;
 }
 void fro_norm(hipStream_t st, int m, int n, const double* X, int ld, double* out,
               double* partials) {

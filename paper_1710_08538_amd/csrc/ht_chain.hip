@@ -20,8 +20,9 @@
 // sums of a reflector step are reduced inside each 32-lane half with DPP row
 // operations and v_permlane16_swap, without LDS.  Per reflector:
 //   1. the wavefront owning column i reduces its norm, forms the reflector
-//      (sign convention of LAPACK's dlarfg: beta = -sign(alpha) ||x||) and
-//      writes v to one of two LDS buffers;
+//      (sign convention of LAPACK's dlarfg: beta = -sign(alpha) ||x||;
+//      columns outside [2^-450, 2^450] are scaled by an exact power of two
+//      first) and writes v to one of two LDS buffers;
 //   2. one workgroup barrier;
 //   3. every wavefront reads v for its rows, forms the four column dots,
 //      reduces them and applies the rank-1 update.
@@ -100,7 +101,7 @@ template <int KMAX>
 __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
                                                        double* __restrict__ X, int ldx, int trans,
                                                        double* __restrict__ Vout,
-                                                       double* __restrict__ Wout) {
+                                                       double* __restrict__ Wout, int ldo) {
   constexpr int RQ = 2 * KMAX / 32;  // rows per lane
   constexpr int CJ = 4;              // columns per lane
   __shared__ double vbuf[2][2 * KMAX];
@@ -149,23 +150,23 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
     ss = readlane_d(half_sum(ss), 32 * hi);
     am = readlane_d(half_max(am), 32 * hi);
     const double alpha = readlane_d(ap, 32 * hi + p / RQ);
-    double xnorm;
-    if (am == 0.0) {
-      xnorm = 0.0;
-    } else if (am > 0x1.0p-450 && am < 0x1.0p450) {
-      xnorm = sqrt(ss);
-    } else {  // rescaled second pass near the ends of the FP64 range
-      const double inv = 1.0 / am;
+    // tiny or huge columns: redo the sum of squares with an exact
+    // power-of-two scaling into the safe range
+    const double sc = safe_scale(fmax(am, fabs(alpha)));
+    if (sc != 1.0) {
       double s2 = 0.0;
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
         const int r = rbase + q;
-        const double t = (r >= x0 && r < x1) ? x[q] * inv : 0.0;
+        const double t = (r >= x0 && r < x1) ? x[q] * sc : 0.0;
         s2 = fma(t, t, s2);
       }
-      xnorm = am * sqrt(readlane_d(half_sum(s2), 32 * hi));
+      ss = readlane_d(half_sum(s2), 32 * hi);
     }
-    const Refl rf = make_refl(alpha, xnorm);
+    const Refl rf0 = make_refl_ss(alpha * sc, ss);
+    Refl rf = rf0;
+    rf.scal = rf0.scal * sc;   // v = x * scal for the unscaled x
+    rf.beta = rf0.beta / sc;
     if (h == hi) {
       double* vb = vbuf[step & 1];
 #pragma unroll
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
         if (r < w) {
           // column i of the factor (R or L) and reflector `step`
           X[tidx(r, i, ldx, trans)] = (r == p) ? rf.beta : (inx ? 0.0 : x[q]);
-          Vout[(size_t)r + (size_t)step * w] = v;
+          Vout[(size_t)r + (size_t)step * ldo] = v;
         }
       }
       if (rl == 0) tbuf[step & 1] = rf.tau;
@@ -244,33 +245,31 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
         const int r = rbase + q;
-        if (r < w) Wout[(size_t)r + (size_t)sc * w] = reg[q][j];
+        if (r < w) Wout[(size_t)r + (size_t)sc * ldo] = reg[q][j];
       }
     }
   }
 }
 
 static void launch_chain(hipStream_t st, int mode, int w, int k, double* tile, int ldt, int trans,
-                         double* Vout, double* Wout) {
+                         double* Vout, double* Wout, int ldo) {
   if (w <= 0 || k <= 0) return;
   if (k <= 64 && w <= 128)
     hipLaunchKernelGGL((k_chain_reg<64>), dim3(1), dim3(512), 0, st, mode, w, k, tile, ldt, trans,
-                       Vout, Wout);
+                       Vout, Wout, ldo);
   else
     hipLaunchKernelGGL((k_chain_reg<128>), dim3(1), dim3(1024), 0, st, mode, w, k, tile, ldt,
-                       trans, Vout, Wout);
+                       trans, Vout, Wout, ldo);
 }
 
 void chain_factor(hipStream_t st, int mode, int w, int k, double* tile, int ldt, double* Vout,
-                  double* Wout, double* Tscratch) {
-  (void)Tscratch;
-  launch_chain(st, mode, w, k, tile, ldt, 0, Vout, Wout);
+                  double* Wout, int ldo) {
+  launch_chain(st, mode, w, k, tile, ldt, 0, Vout, Wout, ldo);
 }
 
 void chain_factor_t(hipStream_t st, int mode, int w, int k, double* tile, int ldt, double* Vout,
-                    double* Wout, double* Tscratch) {
-  (void)Tscratch;
-  launch_chain(st, mode, w, k, tile, ldt, 1, Vout, Wout);
+                    double* Wout, int ldo) {
+  launch_chain(st, mode, w, k, tile, ldt, 1, Vout, Wout, ldo);
 }
 
 }  // namespace htk

@@ -80,10 +80,24 @@ __device__ __forceinline__ double normal_draw(uint64_t seed, uint64_t counter) {
 // remaining entries (LAPACK dlarfg convention): (I - tau v v^T) x = beta e1,
 // beta = -sign(alpha) ||x||, v = x / (alpha - beta) below the pivot.
 struct Refl { double tau, beta, scal; };
-__device__ __forceinline__ Refl make_refl(double alpha, double xnorm) {
+
+// Power-of-two factor that brings a vector whose largest magnitude is amx
+// into [2^-450, 2^450] (1 when it is there already, or zero).  Squares and
+// reciprocals of the scaled entries then neither overflow nor underflow to
+// zero (subnormal entries included), and the scaling itself is exact.
+__device__ __forceinline__ double safe_scale(double amx) {
+  if (amx > 0.0 && amx < 0x1.0p-450) return 0x1.0p600;
+  if (amx > 0x1.0p450) return 0x1.0p-600;
+  return 1.0;
+}
+
+// Householder reflector (LAPACK sign convention, beta = -sign(alpha) ||.||)
+// from the pivot alpha and ss = ||x||^2 of the rest, both of a vector that
+// safe_scale has brought into range: v = [1; x * scal], H = I - tau v v^T.
+__device__ __forceinline__ Refl make_refl_ss(double alpha, double ss) {
   Refl r;
-  if (xnorm == 0.0) { r.tau = 0.0; r.beta = alpha; r.scal = 0.0; return r; }
-  double nrm = hypot(alpha, xnorm);
+  if (ss == 0.0) { r.tau = 0.0; r.beta = alpha; r.scal = 0.0; return r; }
+  const double nrm = sqrt(fma(alpha, alpha, ss));
   r.beta = (alpha >= 0.0) ? -nrm : nrm;
   r.tau = (r.beta - alpha) / r.beta;
   r.scal = 1.0 / (alpha - r.beta);

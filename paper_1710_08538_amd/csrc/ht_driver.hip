@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <vector>
 
@@ -25,29 +26,37 @@ namespace {
 hipError_t g_last_hip = hipSuccess;
 
 // Block structure of the trailing m' = n-j-1 rows/columns for an absorption
-// with k reflectors.  Blocks b_0 = [0, p) and b_t = [p+(t-1)k, p+tk),
-// t = 1..T (Remark 3.3: the first window has p+k rows, the others 2k; p = 0
-// only when m' = k).  The left side mirrors this from the bottom:
-// d_0 = [m'-p, m'), d_t = [m'-p-tk, m'-p-(t-1)k).
+// of k reflectors with block stride s >= k (s = nb).  Blocks b_0 = [0, p) and
+// b_t = [p+(t-1)s, p+ts), t = 1..T; right window t spans the last k rows of
+// b_{t-1} and all of b_t (s+k rows; the first window has p+s, Remark 3.3).
+// The left side mirrors this from the bottom: d_0 = [m'-p, m'),
+// d_t = [m'-p-ts, m'-p-(t-1)s), left window t = d_t and the first k rows of
+// d_{t-1}.  With s = k this is the basic scheme of Sec. 3.3 (2k x k
+// windows).  After an early absorption (k < nb) the stride stays nb, so the
+// chains of V2 and U2 have (m'/nb) windows of k reflectors each, and the
+// restoring chains factor nb x (nb+k) blocks (B's fill band is nb+k wide).
+// When m' <= s there is a single block b_1 = [0, m') and p = 0.
 struct Blocks {
-  int p, T, m, k;
-  int rws(int t) const { return t == 1 ? 0 : p + (t - 2) * k; }  // right window t
-  int rwe(int t) const { return p + t * k; }
-  int rbs(int t) const { return t == 0 ? 0 : p + (t - 1) * k; }  // start of b_t
-  int ds(int t) const { return t == 0 ? m - p : m - p - t * k; }  // d_t
-  int de(int t) const { return t == 0 ? m : m - p - (t - 1) * k; }
+  int p, T, m, k, s;
+  int rbs(int t) const { return t == 0 ? 0 : p + (t - 1) * s; }  // b_t
+  int rbe(int t) const { return t == 0 ? p : std::min(p + t * s, m); }
+  int rws(int t) const { return t == 1 ? 0 : rbs(t) - k; }       // right window t
+  int rwe(int t) const { return rbe(t); }
+  int ds(int t) const { return t == 0 ? m - p : std::max(m - p - t * s, 0); }  // d_t
+  int de(int t) const { return t == 0 ? m : m - p - (t - 1) * s; }
   int lws(int t) const { return ds(t); }                           // left window t
-  int lwe(int t) const { return de(t - 1); }
+  int lwe(int t) const { return t == 1 ? m : de(t) + k; }
 };
 
-Blocks make_blocks(int mprime, int k) {
+Blocks make_blocks(int mprime, int k, int stride) {
   Blocks b;
   b.m = mprime;
   b.k = k;
-  if (mprime == k) { b.p = 0; b.T = 1; return b; }
-  const int q = mprime % k;
-  b.p = q ? q : k;
-  b.T = (mprime - b.p) / k;
+  b.s = std::max(stride, k);
+  if (mprime <= b.s) { b.p = 0; b.T = 1; return b; }
+  const int q = mprime % b.s;
+  b.p = q ? q : b.s;
+  b.T = (mprime - b.p) / b.s;
   return b;
 }
 
@@ -108,9 +117,20 @@ size_t layout(Work* w, int n, int nb, char* base) {
   return off;
 }
 
-// Chain transform t (window width <= 2k, k reflectors) of chain `ch`.
-double* tV(Work& w, int ch, int t, int k) { return w.pool[ch][0] + (size_t)t * 2 * k * k; }
-double* tW(Work& w, int ch, int t, int k) { return w.pool[ch][1] + (size_t)t * 2 * k * k; }
+// Window list of a chain: (start, width, nrefl, slot, roff) in application
+// order.  The transform of a window is kept in slot `slot` of its chain's
+// pool as V, W of 2s x s (column-major, leading dimension 2s) with the real
+// wdt x nrefl factors at row offset roff; the rest is zero.  Right windows
+// are bottom-aligned in the slot (roff = 2s - wdt), left windows top-aligned,
+// so that every full window is a 2s-wide window moving by s.
+struct Win { int a, wdt, k, slot, roff; };
+
+double* tV(Work& w, int ch, const Win& wn, int s) {
+  return w.pool[ch][0] + (size_t)wn.slot * 2 * s * s + wn.roff;
+}
+double* tW(Work& w, int ch, const Win& wn, int s) {
+  return w.pool[ch][1] + (size_t)wn.slot * 2 * s * s + wn.roff;
+}
 
 __global__ void k_add_at(double* x, int idx, double v) { x[idx] += v; }
 __global__ void k_scale_by(double* x, int m, const double* s) {
@@ -190,49 +210,51 @@ struct Ctx {
   int64_t cols_extra_ir = 0, ir_steps = 0, ir_failures = 0, absorptions = 0, columns = 0;
 };
 
-// X(0:rows, window) <- X (I - V W^T), window width wdt, k reflectors.
+// X(0:rows, window) <- X (I - V W^T), window width wdt, k reflectors (V, W
+// with leading dimension ldv).
 void right_apply(Ctx& c, double* X, int ld, int rows, int wdt, int k, const double* Vf,
-                 const double* Wf) {
+                 const double* Wf, int ldv) {
   if (rows <= 0 || wdt <= 0 || k <= 0) return;
   const int pi = c.prof.begin(c.st, HT_PROF_WY);
-  gemm(c.st, false, false, rows, k, wdt, 1.0, X, ld, Vf, wdt, 0.0, c.w->P, c.n);
-  gemm(c.st, false, true, rows, wdt, k, -1.0, c.w->P, c.n, Wf, wdt, 1.0, X, ld);
+  gemm(c.st, false, false, rows, k, wdt, 1.0, X, ld, Vf, ldv, 0.0, c.w->P, c.n);
+  gemm(c.st, false, true, rows, wdt, k, -1.0, c.w->P, c.n, Wf, ldv, 1.0, X, ld);
   c.prof.end(c.st, pi, 4.0 * rows * (double)wdt * k);
   c.flops += 4.0 * rows * (double)wdt * k;
 }
 
 // X(window, 0:ncols) <- (I - V W^T)^T X = X - W (V^T X).
 void left_apply(Ctx& c, double* X, int ld, int ncols, int wdt, int k, const double* Vf,
-                const double* Wf) {
+                const double* Wf, int ldv) {
   if (ncols <= 0 || wdt <= 0 || k <= 0) return;
   const int pi = c.prof.begin(c.st, HT_PROF_WY);
-  gemm(c.st, true, false, k, ncols, wdt, 1.0, Vf, wdt, X, ld, 0.0, c.w->P, k);
-  gemm(c.st, false, false, wdt, ncols, k, -1.0, Wf, wdt, c.w->P, k, 1.0, X, ld);
+  gemm(c.st, true, false, k, ncols, wdt, 1.0, Vf, ldv, X, ld, 0.0, c.w->P, k);
+  gemm(c.st, false, false, wdt, ncols, k, -1.0, Wf, ldv, c.w->P, k, 1.0, X, ld);
   c.prof.end(c.st, pi, 4.0 * ncols * (double)wdt * k);
   c.flops += 4.0 * ncols * (double)wdt * k;
 }
 
-// Window list of a chain: (start, width, nrefl, slot) in application order.
-struct Win { int a, wdt, k, slot; };
-
 std::vector<Win> right_windows(const Blocks& bl, int chain) {
   std::vector<Win> v;
+  auto win = [&](int a, int e, int nr, int t) {
+    v.push_back({a, e - a, nr, t, 2 * bl.s - (e - a)});
+  };
   if (chain == 0) {  // Q^_1 .. Q^_T (QL of V2), applied first to last
-    for (int t = 1; t <= bl.T; ++t) v.push_back({bl.rws(t), bl.rwe(t) - bl.rws(t), bl.k, t});
-  } else {           // RQ restore G_T .. G_1, G_0
-    for (int t = bl.T; t >= 1; --t) v.push_back({bl.rws(t), bl.rwe(t) - bl.rws(t), bl.k, t});
-    if (bl.p > 0) v.push_back({0, bl.p, bl.p, 0});
+    for (int t = 1; t <= bl.T; ++t) win(bl.rws(t), bl.rwe(t), bl.k, t);
+  } else {           // RQ restore G_T .. G_1, G_0 (nrefl = rows of b_t)
+    for (int t = bl.T; t >= 1; --t) win(bl.rws(t), bl.rwe(t), bl.rbe(t) - bl.rbs(t), t);
+    if (bl.p > 0) win(0, bl.p, bl.p, 0);
   }
   return v;
 }
 
 std::vector<Win> left_windows(const Blocks& bl, int chain) {
   std::vector<Win> v;
+  auto win = [&](int a, int e, int nr, int t) { v.push_back({a, e - a, nr, t, 0}); };
   if (chain == 2) {  // Q~_1 .. Q~_T (QR of U2, bottom to top)
-    for (int t = 1; t <= bl.T; ++t) v.push_back({bl.lws(t), bl.lwe(t) - bl.lws(t), bl.k, t});
-  } else {           // QR restore H_T .. H_1, H_0
-    for (int t = bl.T; t >= 1; --t) v.push_back({bl.lws(t), bl.lwe(t) - bl.lws(t), bl.k, t});
-    if (bl.p > 0) v.push_back({bl.ds(0), bl.p, bl.p, 0});
+    for (int t = 1; t <= bl.T; ++t) win(bl.lws(t), bl.lwe(t), bl.k, t);
+  } else {           // QR restore H_T .. H_1, H_0 (nrefl = columns of d_t)
+    for (int t = bl.T; t >= 1; --t) win(bl.lws(t), bl.lwe(t), bl.de(t) - bl.ds(t), t);
+    if (bl.p > 0) win(bl.ds(0), bl.m, bl.p, 0);
   }
   return v;
 }
@@ -249,17 +271,24 @@ struct RJob { double* X; int ld; int rows; bool tri; int tri_off; };
 // chain (first window p+k wide, last one p x p) use the generic product.
 void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, int chain,
                 const std::vector<Win>& wins) {
-  const int k = bl.k;
+  const int s = bl.s, K = bl.s;
+  // a full window: its 2s-wide slot window (the real window plus zero
+  // padding) lies inside the trailing part; consecutive full windows move by s
+  auto slot_start = [&](const Win& w) { return w.a - w.roff; };
+  auto full_win = [&](const Win& w) {
+    const int a0 = slot_start(w);
+    return a0 >= 0 && a0 + 2 * s <= bl.m;
+  };
   size_t i = 0;
   while (i < wins.size()) {
     const Win& w0 = wins[i];
-    const bool full = sweep_supported(k) && jobs.size() <= 4 && w0.wdt == 2 * k && w0.k == k;
+    const bool full = sweep_supported(K) && jobs.size() <= 4 && full_win(w0);
     size_t e = i + 1;
     int dir = 0;
     if (full) {
-      while (e < wins.size() && wins[e].wdt == 2 * k && wins[e].k == k) {
-        const int d = wins[e].a - wins[e - 1].a;
-        if (!((d == k || d == -k) && (dir == 0 || d == dir * k))) break;
+      while (e < wins.size() && full_win(wins[e])) {
+        const int d = slot_start(wins[e]) - slot_start(wins[e - 1]);
+        if (!((d == s || d == -s) && (dir == 0 || d == dir * s))) break;
         dir = d > 0 ? 1 : -1;
         ++e;
       }
@@ -280,22 +309,22 @@ void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, 
         wg += (jb.rows + 63) / 64;
       }
       sa.nwin = (int)(e - i);
-      sa.c0 = j + 1 + w0.a;
+      sa.c0 = j + 1 + slot_start(w0);
       sa.Vp = c.w->pool[chain][0];
       sa.Wp = c.w->pool[chain][1];
       sa.slot0 = w0.slot;
       sa.slot_step = wins[i + 1].slot - w0.slot;
-      double fl = 0.0;
+      double fl = 0.0;  // algorithmic: 4 rows wdt nrefl per window
       for (const RJob& jb : jobs) {
         if (jb.rows <= 0) continue;
         for (size_t t = i; t < e; ++t) {  // B: rows below a window's end are zero
-          const int r = jb.tri ? std::max(0, std::min(jb.rows, j + 1 + wins[t].a + 2 * k - jb.tri_off))
+          const int r = jb.tri ? std::max(0, std::min(jb.rows, j + 1 + wins[t].a + wins[t].wdt - jb.tri_off))
                                : jb.rows;
-          fl += 8.0 * r * (double)k * k;
+          fl += 4.0 * r * (double)wins[t].wdt * wins[t].k;
         }
       }
       const int pi = c.prof.begin(c.st, HT_PROF_SWEEP);
-      sweep_rows(c.st, sa, k, dir);
+      sweep_rows(c.st, sa, K, dir);
       c.prof.end(c.st, pi, fl);
       c.flops += fl;
       i = e;
@@ -305,7 +334,7 @@ void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, 
       if (jb.rows <= 0) continue;
       const int r = jb.tri ? std::min(jb.rows, j + 1 + w0.a + w0.wdt - jb.tri_off) : jb.rows;
       right_apply(c, at(jb.X, jb.ld, 0, j + 1 + w0.a), jb.ld, r, w0.wdt, w0.k,
-                  tV(*c.w, chain, w0.slot, k), tW(*c.w, chain, w0.slot, k));
+                  tV(*c.w, chain, w0, s), tW(*c.w, chain, w0, s), 2 * s);
     }
     ++i;
   }
@@ -323,7 +352,7 @@ void sweep_left(Ctx& c, double* X, int ld, int c0, bool tri, int j, const Blocks
   for (const Win& wn : left_windows(bl, chain)) {
     const int cs = tri ? std::max(c0, j + 1 + wn.a) : c0;
     left_apply(c, at(X, ld, j + 1 + wn.a, cs), ld, c.n - cs, wn.wdt, wn.k,
-               tV(*c.w, chain, wn.slot, bl.k), tW(*c.w, chain, wn.slot, bl.k));
+               tV(*c.w, chain, wn, bl.s), tW(*c.w, chain, wn, bl.s), 2 * bl.s);
   }
 }
 
@@ -333,12 +362,13 @@ void sweep_cols_right(Ctx& c, double* X, int ld, int rows, int j, const Blocks& 
 }
 
 // One chain factorisation, timed as HT_PROF_CHAIN (flops of a Householder
-// QR/QL of a wdt x k tile plus the W build: about 4 wdt k^2).
+// QR/QL of a wdt x k tile plus the W build: about 4 wdt k^2).  V and W are
+// written with leading dimension ldo.
 void chain(Ctx& c, int mode, bool trans, int wdt, int k, double* tile, int ld, double* Vf,
-           double* Wf) {
+           double* Wf, int ldo) {
   const int pi = c.prof.begin(c.st, HT_PROF_CHAIN);
-  if (trans) chain_factor_t(c.st, mode, wdt, k, tile, ld, Vf, Wf, c.w->Gws);
-  else chain_factor(c.st, mode, wdt, k, tile, ld, Vf, Wf, c.w->Gws);
+  if (trans) chain_factor_t(c.st, mode, wdt, k, tile, ld, Vf, Wf, ldo);
+  else chain_factor(c.st, mode, wdt, k, tile, ld, Vf, Wf, ldo);
   c.prof.end(c.st, pi, 4.0 * wdt * (double)k * k);
   c.flops += 4.0 * wdt * (double)k * k;
 }
@@ -395,33 +425,37 @@ void residual(Ctx& c, int s, int kk, const double* x, const double* rhs) {
   c.flops += 1.0 * L * (double)L + 4.0 * L * (double)(2 * kk + 1);
 }
 
+
 // ---------------------------------------------------------------------------
 // Absorption of k left and right reflectors (Sec. 3.3).
 // ---------------------------------------------------------------------------
 void absorb(Ctx& c, int s, int k) {
   Work& w = *c.w;
   const int n = c.n, j = s + k, L = n - s - 1, mp = n - j - 1;
-  const Blocks bl = make_blocks(mp, k);
+  const Blocks bl = make_blocks(mp, k, c.nb);
+  const int sb = bl.s, ldo = 2 * bl.s;
   double *A = c.A, *B = c.B;
   const int lda = c.lda, ldb = c.ldb;
   c.absorptions++;
+  // windows narrower than their 2s slot: clear the slots' padding
+  if (k < sb) {
+    const size_t slots = (size_t)(bl.T + 1) * 2 * sb * sb;
+    for (int ch = 0; ch < 4; ++ch)
+      for (int v = 0; v < 2; ++v) zero_mat(c.st, w.pool[ch][v], (int)slots, 1, (int)slots);
+  }
 
   // (3.3.1 b) V2 = Q^_1 ... Q^_T [0; L1]: QL chain, top to bottom, in place.
   double* V2 = w.V + k;
-  for (int t = 1; t <= bl.T; ++t) {
-    const int a = bl.rws(t), e = bl.rwe(t);
-    chain(c, 1, false, e - a, k, V2 + a, n, tV(w, 0, t, k), tW(w, 0, t, k));
-  }
+  for (const Win& wn : right_windows(bl, 0))
+    chain(c, 1, false, wn.wdt, k, V2 + wn.a, n, tV(w, 0, wn, sb), tW(w, 0, wn, sb), ldo);
   const double* L1 = w.V + (L - k);
   const double* V1 = w.V;
 
   // (3.3.2 b) U2 = Q~_1 ... Q~_T [R1; 0]: QR chain, bottom to top, on a copy
   // (the spike update below needs the original U2).
   copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
-  for (int t = 1; t <= bl.T; ++t) {
-    const int a = bl.lws(t), e = bl.lwe(t);
-    chain(c, 0, false, e - a, k, w.Ucp + a, n, tV(w, 2, t, k), tW(w, 2, t, k));
-  }
+  for (const Win& wn : left_windows(bl, 2))
+    chain(c, 0, false, wn.wdt, k, w.Ucp + wn.a, n, tV(w, 2, wn, sb), tW(w, 2, wn, sb), ldo);
   copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
   copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
 
@@ -460,13 +494,12 @@ void absorb(Ctx& c, int s, int k) {
   // block of row block b_t is factored as [0 R] G_t; G_t^T is applied to
   // the rows above it at once (the next step needs row block b_{t-1}).
   for (const Win& wn : right_windows(bl, 1)) {
-    const int t = wn.slot;
-    const int r0 = (t == 0) ? 0 : bl.rbs(t);
-    const int kr = (t == 0) ? bl.p : k;  // rows of the block
+    const int r0 = bl.rbs(wn.slot);
+    const int kr = wn.k;  // rows of the block
     double* C = at(B, ldb, j + 1 + r0, j + 1 + wn.a);
-    chain(c, 1, true, wn.wdt, kr, C, ldb, tV(w, 1, t, k), tW(w, 1, t, k));
-    right_apply(c, at(B, ldb, 0, j + 1 + wn.a), ldb, j + 1 + r0, wn.wdt, kr, tV(w, 1, t, k),
-                tW(w, 1, t, k));
+    chain(c, 1, true, wn.wdt, kr, C, ldb, tV(w, 1, wn, sb), tW(w, 1, wn, sb), ldo);
+    right_apply(c, at(B, ldb, 0, j + 1 + wn.a), ldb, j + 1 + r0, wn.wdt, kr, tV(w, 1, wn, sb),
+                tW(w, 1, wn, sb), ldo);
   }
   {
     std::vector<RJob> jobs{RJob{A, lda, n, false, 0}};
@@ -519,9 +552,9 @@ void absorb(Ctx& c, int s, int k) {
     const int t = wn.slot;
     const int cs = bl.ds(t), ce = bl.de(t);  // columns d_t
     double* M = at(B, ldb, j + 1 + wn.a, j + 1 + cs);
-    chain(c, 0, false, wn.wdt, ce - cs, M, ldb, tV(w, 3, t, k), tW(w, 3, t, k));
+    chain(c, 0, false, wn.wdt, ce - cs, M, ldb, tV(w, 3, wn, sb), tW(w, 3, wn, sb), ldo);
     left_apply(c, at(B, ldb, j + 1 + wn.a, j + 1 + ce), ldb, mp - ce, wn.wdt, ce - cs,
-               tV(w, 3, t, k), tW(w, 3, t, k));
+               tV(w, 3, wn, sb), tW(w, 3, wn, sb), ldo);
   }
   sweep_left(c, A, lda, j, false, j, bl, 3);
   if (c.wantQ) sweep_cols_right(c, c.Q, c.ldq, n, j, bl, 3);

@@ -85,18 +85,19 @@ void ir_residual(hipStream_t st, int m, const double* w, const double* c,
 void ir_update(hipStream_t st, int m, double* x, const double* d, const int* E2,
                int* Erhs);
 
-// Chain factorisation of a w x k tile (w <= 2*KMAX) held in global memory.
-// mode 0: QR (tile = Qf [R; 0]), mode 1: QL (tile = Qf [0; L]).
+// Chain factorisation of a w x k tile (w <= 256, k <= 128) held in global
+// memory.  mode 0: QR (tile = Qf [R; 0]), mode 1: QL (tile = Qf [0; L]).
 // On exit the tile holds R (resp. L) with exact zeros elsewhere, and
-// Qf = I - V W^T with V, W (w x k, ld w) written to Vout, Wout.
+// Qf = I - V W^T with V, W (w x k, leading dimension ldo >= w) written to
+// Vout, Wout.
 void chain_factor(hipStream_t st, int mode, int w, int k, double* tile, int ldt,
-                  double* Vout, double* Wout, double* Tscratch);
+                  double* Vout, double* Wout, int ldo);
 
 // Same as chain_factor but the tile is given transposed: the kernel factors
 // X = tile^T (w x k), tile is k x w with leading dimension ldt, and the
 // result factor is written back transposed.
 void chain_factor_t(hipStream_t st, int mode, int w, int k, double* tile, int ldt,
-                    double* Vout, double* Wout, double* Tscratch);
+                    double* Vout, double* Wout, int ldo);
 
 int num_cus();
 

@@ -17,31 +17,33 @@ static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b)
 __global__ __launch_bounds__(1024) void k_house(int m, double* x, double* v, double* tau_out,
                                                 double* beta_out, int overwrite) {
   __shared__ double sh[16];
+  const double alpha = x[0];
   double amax = 0.0;
   for (int i = 1 + threadIdx.x; i < m; i += 1024) amax = fmax(amax, fabs(x[i]));
   amax = block_max(amax, sh);
+  // exact power-of-two scaling into the safe range (tiny or huge columns)
+  const double sc = safe_scale(fmax(amax, fabs(alpha)));
   double ss = 0.0;
   if (amax > 0.0) {
-    const double inv = 1.0 / amax;
     for (int i = 1 + threadIdx.x; i < m; i += 1024) {
-      double t = x[i] * inv;
+      const double t = x[i] * sc;
       ss = fma(t, t, ss);
     }
   }
   ss = block_sum(ss, sh);
-  const double alpha = x[0];
-  const double xnorm = amax * sqrt(ss);
-  const Refl r = make_refl(alpha, xnorm);
+  const Refl r = make_refl_ss(alpha * sc, ss);
+  const double f = sc * r.scal;
   for (int i = 1 + threadIdx.x; i < m; i += 1024) {
     double xi = x[i];
-    v[i] = xi * r.scal;
+    v[i] = xi * f;
     if (overwrite) x[i] = 0.0;
   }
   if (threadIdx.x == 0) {
+    const double beta = r.beta / sc;
     v[0] = 1.0;
-    if (overwrite) x[0] = r.beta;
+    if (overwrite) x[0] = beta;
     tau_out[0] = r.tau;
-    beta_out[0] = r.beta;
+    beta_out[0] = beta;
   }
 }
 
@@ -117,7 +119,8 @@ __global__ __launch_bounds__(1024) void k_ir_residual(int m, const double* w, co
   rmax = block_max(rmax, sh);
   xmax = block_max(xmax, sh);
   double rs = 0.0, xs = 0.0;
-  const double ir = rmax > 0.0 ? 1.0 / rmax : 0.0, ix = xmax > 0.0 ? 1.0 / xmax : 0.0;
+  // exact power-of-two scalings (subnormal or huge entries are safe)
+  const double ir = safe_scale(rmax), ix = safe_scale(xmax);
   for (int i = threadIdx.x; i < m; i += 1024) {
     double a = r[i] * ir, b = x[i] * ix;
     rs = fma(a, a, rs);
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(1024) void k_ir_residual(int m, const double* w, co
   rs = block_sum(rs, sh);
   xs = block_sum(xs, sh);
   if (threadIdx.x == 0) {
-    const double rn = rmax * sqrt(rs), xn = xmax * sqrt(xs);
+    const double rn = sqrt(rs) / ir, xn = sqrt(xs) / ix;
     norms[0] = rn;
     norms[1] = xn;
     const double tol = tol_factor * kUnitRoundoff * normB[0];

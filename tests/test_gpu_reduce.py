@@ -119,6 +119,20 @@ def test_zero_diagonal_and_zero_B():
     assert inv["zeros_H"] == 0 and inv["bwd_A"] <= 1e-14 * n
 
 
+@pytest.mark.parametrize("e2", [-900, -600, 900])
+def test_extreme_scaling(e2):
+    """A and B scaled by 2^e2 (tiny or huge entries, up to 2^+-900): the
+    reflectors and solves scale exactly, so H / 2^e2 and T / 2^e2 must meet
+    the invariants of the unscaled pencil."""
+    n = 150
+    A0, B0 = inputs.random_pencil(n, seed=21)
+    f = np.ldexp(1.0, e2)
+    got, st = run_gpu(np.asfortranarray(A0 * f), np.asfortranarray(B0 * f), nb=16)
+    assert all(np.isfinite(M).all() for M in got)
+    H, T, Q, Z = got
+    assert_invariants(A0, B0, (H / f, T / f, Q, Z))
+
+
 def test_nonfinite_input_rejected():
     n = 16
     A0, B0 = inputs.random_pencil(n, seed=9)
