@@ -138,16 +138,29 @@ def main():
     prof_work = [sum(s["prof_work"][c] for s in pstats) for c in range(ncls)]
     prof_l = [sum(s["prof_launches"][c] for s in pstats) for c in range(ncls)]
     dom = max(range(ncls), key=lambda c: prof_ms[c])
-    if htred.PROF_CLASSES[dom] in ("wy", "chain", "sweep"):
-        achieved = prof_work[dom] / (prof_ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
-    else:
-        achieved = prof_work[dom] / (prof_ms[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["kernel_class"] = htred.PROF_CLASSES[dom]
-    roof["launches_per_step"] = prof_l[dom]
+
+    def roofline_of(c):
+        name = htred.PROF_CLASSES[c]
+        if prof_ms[c] <= 0.0:
+            return None
+        if name in ("trsv", "trmv", "ygemv"):  # work = algorithmic bytes
+            a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e9
+            r = {"bound": "hbm", "achieved": a, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        elif name == "sweep":                  # FP64 MFMA
+            a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
+            r = {"bound": "mfma", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+        else:                                  # chains, generic products: FP64 vector ALU
+            a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
+            r = {"bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = None
+        r["kernel_class"] = name
+        r["launches_per_step"] = prof_l[c]
+        r["avg_launch_us"] = 1000.0 * prof_ms[c] / max(prof_l[c], 1)
+        return r
+
+    roof = roofline_of(dom)
+    by_class = {htred.PROF_CLASSES[c]: roofline_of(c) for c in range(ncls)}
     breakdown = {htred.PROF_CLASSES[c]: {"ms": prof_ms[c], "launches": prof_l[c],
                                          "work": prof_work[c]}
                  for c in range(ncls)}
@@ -174,6 +187,7 @@ def main():
                                          "absorptions", "scaled_solves")},
         "profiled_step": breakdown,
         "roofline": roof,
+        "roofline_by_class": by_class,
     }
     if not args.no_check:
         inv = checks.invariants(A0d, B0d, A, B, Q, Z)
