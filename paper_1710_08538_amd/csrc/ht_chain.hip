@@ -98,10 +98,13 @@ __device__ __forceinline__ double half_max(double x) {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <int KMAX>
-__global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
-                                                       double* __restrict__ X, int ldx, int trans,
-                                                       double* __restrict__ Vout,
-                                                       double* __restrict__ Wout, int ldo) {
+__global__ __launch_bounds__(KMAX * 8) void k_chain_reg(ChainJobs jobs) {
+  // one tile per workgroup
+  const ChainJob& jb = jobs.job[blockIdx.x];
+  const int mode = jb.mode, w = jb.w, k = jb.k, ldx = jb.ldx, trans = jb.trans, ldo = jb.ldo;
+  double* __restrict__ X = jb.X;
+  double* __restrict__ Vout = jb.V;
+  double* __restrict__ Wout = jb.W;
   constexpr int RQ = 2 * KMAX / 32;  // rows per lane
   constexpr int CJ = 4;              // columns per lane
   __shared__ double vbuf[2][2 * KMAX];
@@ -251,15 +254,24 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(int mode, int w, int k,
   }
 }
 
+void chain_factor_jobs(hipStream_t st, const ChainJobs& jobs) {
+  if (jobs.njobs <= 0) return;
+  bool small = true;
+  for (int i = 0; i < jobs.njobs; ++i)
+    small = small && jobs.job[i].k <= 64 && jobs.job[i].w <= 128;
+  if (small)
+    hipLaunchKernelGGL((k_chain_reg<64>), dim3(jobs.njobs), dim3(512), 0, st, jobs);
+  else
+    hipLaunchKernelGGL((k_chain_reg<128>), dim3(jobs.njobs), dim3(1024), 0, st, jobs);
+}
+
 static void launch_chain(hipStream_t st, int mode, int w, int k, double* tile, int ldt, int trans,
                          double* Vout, double* Wout, int ldo) {
   if (w <= 0 || k <= 0) return;
-  if (k <= 64 && w <= 128)
-    hipLaunchKernelGGL((k_chain_reg<64>), dim3(1), dim3(512), 0, st, mode, w, k, tile, ldt, trans,
-                       Vout, Wout, ldo);
-  else
-    hipLaunchKernelGGL((k_chain_reg<128>), dim3(1), dim3(1024), 0, st, mode, w, k, tile, ldt,
-                       trans, Vout, Wout, ldo);
+  ChainJobs jobs;
+  jobs.njobs = 1;
+  jobs.job[0] = ChainJob{mode, w, k, tile, ldt, trans, Vout, Wout, ldo};
+  chain_factor_jobs(st, jobs);
 }
 
 void chain_factor(hipStream_t st, int mode, int w, int k, double* tile, int ldt, double* Vout,

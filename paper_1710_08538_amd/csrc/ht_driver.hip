@@ -444,18 +444,30 @@ void absorb(Ctx& c, int s, int k) {
       for (int v = 0; v < 2; ++v) zero_mat(c.st, w.pool[ch][v], (int)slots, 1, (int)slots);
   }
 
-  // (3.3.1 b) V2 = Q^_1 ... Q^_T [0; L1]: QL chain, top to bottom, in place.
+  // (3.3.1 b) V2 = Q^_1 ... Q^_T [0; L1]: QL chain, top to bottom, in place;
+  // (3.3.2 b) U2 = Q~_1 ... Q~_T [R1; 0]: QR chain, bottom to top, on a copy
+  // (the spike update below needs the original U2).  The two chains are
+  // independent and have the same windows count: window t of both is
+  // factored in one launch on two workgroups.
   double* V2 = w.V + k;
-  for (const Win& wn : right_windows(bl, 0))
-    chain(c, 1, false, wn.wdt, k, V2 + wn.a, n, tV(w, 0, wn, sb), tW(w, 0, wn, sb), ldo);
+  copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
+  {
+    const std::vector<Win> r0 = right_windows(bl, 0), l2 = left_windows(bl, 2);
+    for (size_t t = 0; t < r0.size(); ++t) {
+      const Win &a = r0[t], &b = l2[t];
+      ChainJobs jobs;
+      jobs.njobs = 2;
+      jobs.job[0] = ChainJob{1, a.wdt, k, V2 + a.a, n, 0, tV(w, 0, a, sb), tW(w, 0, a, sb), ldo};
+      jobs.job[1] = ChainJob{0, b.wdt, k, w.Ucp + b.a, n, 0, tV(w, 2, b, sb), tW(w, 2, b, sb), ldo};
+      const int pi = c.prof.begin(c.st, HT_PROF_CHAIN);
+      chain_factor_jobs(c.st, jobs);
+      const double fl = 4.0 * (a.wdt + b.wdt) * (double)k * k;
+      c.prof.end(c.st, pi, fl);
+      c.flops += fl;
+    }
+  }
   const double* L1 = w.V + (L - k);
   const double* V1 = w.V;
-
-  // (3.3.2 b) U2 = Q~_1 ... Q~_T [R1; 0]: QR chain, bottom to top, on a copy
-  // (the spike update below needs the original U2).
-  copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
-  for (const Win& wn : left_windows(bl, 2))
-    chain(c, 0, false, wn.wdt, k, w.Ucp + wn.a, n, tV(w, 2, wn, sb), tW(w, 2, wn, sb), ldo);
   copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
   copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
 

@@ -99,6 +99,21 @@ void chain_factor(hipStream_t st, int mode, int w, int k, double* tile, int ldt,
 void chain_factor_t(hipStream_t st, int mode, int w, int k, double* tile, int ldt,
                     double* Vout, double* Wout, int ldo);
 
+// Several independent chain factorisations in one launch (one workgroup
+// each; at most 2).  A job with w <= 0 or k <= 0 is not allowed here.
+struct ChainJob {
+  int mode, w, k;
+  double* X;
+  int ldx, trans;
+  double *V, *W;
+  int ldo;
+};
+struct ChainJobs {
+  ChainJob job[2];
+  int njobs;
+};
+void chain_factor_jobs(hipStream_t st, const ChainJobs& jobs);
+
 int num_cus();
 
 }  // namespace htk
