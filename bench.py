@@ -64,6 +64,64 @@ def cpu_baseline(A0, B0, target_s):
             "time_s_extrapolated": t_full}
 
 
+def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
+    """The batched workload: `count` pencils with orders U{32..512} (child seeds
+    of SeedSequence(seed)), reduced in one persistent launch; timed eagerly and
+    as a hipGraph replay, inputs restored from device copies before each run."""
+    sizes = inputs.batch_sizes(count, seed)
+    pencils = inputs.batch_pencils(count, seed)
+    A0s = [htred.to_device_colmajor(A) for A, _ in pencils]
+    B0s = [htred.to_device_colmajor(B) for _, B in pencils]
+    As = [htred.to_device_colmajor(A) for A, _ in pencils]
+    Bs = [htred.to_device_colmajor(B) for _, B in pencils]
+    Qs = [htred.colmajor_empty(A.shape[0]) for A in As]
+    Zs = [htred.colmajor_empty(A.shape[0]) for A in As]
+    plan = htred.BatchedPlan(As, Bs, Qs, Zs)
+
+    def restore():
+        for i in range(count):
+            As[i].copy_(A0s[i])
+            Bs[i].copy_(B0s[i])
+
+    restore()
+    plan.run()
+    torch.cuda.synchronize()
+    restore()
+    torch.cuda.synchronize()
+    t = time.time()
+    plan.run()
+    torch.cuda.synchronize()
+    eager_s = time.time() - t
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream()
+    restore()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            plan.run(stream=st)
+    torch.cuda.current_stream().wait_stream(st)
+    restore()
+    torch.cuda.synchronize()
+    t = time.time()
+    g.replay()
+    torch.cuda.synchronize()
+    graph_s = time.time() - t
+    info = plan.info[:count].cpu().numpy()
+    worst = {"bwd_A": 0.0, "bwd_B": 0.0, "orth_Q": 0.0, "orth_Z": 0.0}
+    ok = bool((info == 0).all())
+    for i in range(0, count, 32):
+        inv = checks.invariants(A0s[i], B0s[i], As[i], Bs[i], Qs[i], Zs[i])
+        ok = ok and bool(checks.invariants_ok(inv, int(sizes[i])))
+        for k in worst:
+            worst[k] = max(worst[k], float(inv[k]))
+    fl = float(sum(39.0 * float(n) ** 3 for n in sizes))
+    return {"pencils": count, "orders": "U{32..512}", "seed": seed,
+            "ms": 1000.0 * eager_s, "pencils_per_s": count / eager_s,
+            "gflops_nominal": fl / eager_s / 1e9, "graph_replay_ms": 1000.0 * graph_s,
+            "checked_sample": len(range(0, count, 32)), "invariants_ok": ok,
+            "backward_error_max": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +134,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched form measured beside the headline run")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -196,6 +256,10 @@ def main():
         result["invariants_ok"] = bool(checks.invariants_ok(inv, n))
     del A0d, B0d, A, B, Q, Z, ws
     torch.cuda.empty_cache()
+    if not args.no_forms:
+        print("bench: batched form ...", file=sys.stderr, flush=True)
+        result["forms"] = {"batched": batched_form(torch, htred, inputs, checks)}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         print("bench: cpu baseline ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(A0, B0, args.cpu_seconds)

@@ -1,0 +1,635 @@
+// ht_batched.hip -- many independent HT reductions of small pencils in one
+// persistent launch (the batched form; small pencils of uneven order arise
+// e.g. as deflation windows of the QZ algorithm, Sec. 1).
+//
+// Each pencil (order n <= 512) is reduced by one 256-thread workgroup with
+// Algorithm 1: the panel reduction of Sec. 3.2 (column update a, left
+// reflector b, factored solve with iterative refinement c, opposite
+// reflector and Y column d) over all columns as one panel, followed by an
+// absorption in which the accumulated block reflectors
+//   Q = I - U S U^T,  Z = I - V T V^T  (Sec. 2.4)
+// are applied to B, Q, Z and the not yet reduced part of A as plain dense
+// products.  Within one panel B is never modified (Sec. 3.2), so its solves
+// use the triangular input B; after the last column the two-sided product
+// (I - U S^T U^T) B (I - V T V^T) is triangular up to rounding (Lemma 2.1
+// for every reduced column), and its strict lower part is set to zero as in
+// Algorithm 2.  When iterative refinement fails for column j (Algorithm 1),
+// the column is restored, the j-s accumulated pairs are absorbed in the
+// same way, the trailing block B(j+1:n, j+1:n) is brought back to
+// triangular form by a Householder QR whose transformations are applied to
+// A (rows j+1..n-1) and Q, and a new panel starts at column j.
+//
+// Scheduling: a one-workgroup kernel sorts the pencils by decreasing order
+// (counting sort on n) and resets the work counter; the persistent kernel's
+// workgroups then take pencils in that order from an atomic ticket, so the
+// largest pencils start first.  Nothing is read back by the host: the two
+// launches can be captured in a hipGraph.  Solves are scaled as in the
+// single-pencil path (a power-of-two exponent; rescaling by 2^-600 before
+// any entry of x exceeds 2^600 times its pivot).
+#include "../../include/htred.h"
+#include "ht_device.h"
+#include "ht_internal.h"
+
+namespace htk {
+
+namespace {
+
+constexpr int kBT = 256;  // threads per pencil workgroup
+constexpr int kBNW = kBT / 64;
+constexpr int kBMax = 512;
+
+struct BatchArgs {
+  int batch, nmax, max_ir;
+  const int32_t* n;
+  double* const* A;
+  double* const* B;
+  double* const* Q;
+  double* const* Z;
+  const int32_t* ld;
+  int32_t* info;
+  int* counter;
+  int* order;
+  double* scratch;      // per workgroup: scratch_stride doubles
+  size_t scratch_stride;
+  double tol_factor;
+  uint64_t seed;
+};
+
+// Per-pencil scratch (global memory, leading dimension nmax).
+struct BWork {
+  double *U, *V, *Y, *S, *T, *P, *P2;
+  double *ctil, *ysol, *dsol, *wv, *w2, *rv, *acol, *tk, *tk2;
+  int ld;
+};
+
+__device__ BWork bwork(double* base, int nmax) {
+  BWork w;
+  const size_t sq = (size_t)nmax * nmax;
+  w.ld = nmax;
+  w.U = base;
+  w.V = w.U + sq;
+  w.Y = w.V + sq;
+  w.S = w.Y + sq;
+  w.T = w.S + sq;
+  w.P = w.T + sq;
+  w.P2 = w.P + sq;
+  double* v = w.P2 + sq;
+  w.ctil = v; v += nmax;
+  w.ysol = v; v += nmax;
+  w.dsol = v; v += nmax;
+  w.wv = v; v += nmax;
+  w.w2 = v; v += nmax;
+  w.rv = v; v += nmax;
+  w.acol = v; v += nmax;
+  w.tk = v; v += nmax;
+  w.tk2 = v; v += nmax;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-level building blocks.  Every one ends with a barrier, so its
+// global-memory results are visible to the whole workgroup.
+// ---------------------------------------------------------------------------
+
+__device__ void wg_fill(double* x, int m, double v) {
+  for (int i = threadIdx.x; i < m; i += kBT) x[i] = v;
+  __syncthreads();
+}
+__device__ void wg_copy(double* y, const double* x, int m) {
+  for (int i = threadIdx.x; i < m; i += kBT) y[i] = x[i];
+  __syncthreads();
+}
+__device__ void wg_zero_mat(double* X, int m, int n, int ld) {
+  for (int c = 0; c < n; ++c)
+    for (int i = threadIdx.x; i < m; i += kBT) X[i + (size_t)c * ld] = 0.0;
+  __syncthreads();
+}
+
+// y(0:m) = alpha X(0:m, 0:k) x + beta y   (x with stride incx; y distinct
+// from X and x)
+__device__ void wg_gemv_n(int m, int k, double alpha, const double* X, int ldx, const double* x,
+                          int incx, double beta, double* y) {
+  for (int i = threadIdx.x; i < m; i += kBT) {
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s = fma(X[i + (size_t)c * ldx], x[(size_t)c * incx], s);
+    y[i] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[i]);
+  }
+  __syncthreads();
+}
+
+// z(0:k) = alpha X(0:m, 0:k)^T x + beta z: one wavefront per column
+__device__ void wg_gemv_t(int m, int k, double alpha, const double* X, int ldx, const double* x,
+                          double beta, double* z) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c = wv; c < k; c += kBNW) {
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s = fma(X[i + (size_t)c * ldx], x[i], s);
+    s = wave_sum(s);
+    if (lane == 0) z[c] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * z[c]);
+  }
+  __syncthreads();
+}
+
+// y = alpha op(T) x for upper triangular T (k x k); y distinct from x
+__device__ void wg_trmv_small(bool trans, int k, const double* T, int ldt, const double* x,
+                              double alpha, double* y) {
+  for (int t = threadIdx.x; t < k; t += kBT) {
+    double s = 0.0;
+    if (!trans) {
+      for (int c = t; c < k; ++c) s = fma(T[t + (size_t)c * ldt], x[c], s);
+    } else {
+      for (int c = 0; c <= t; ++c) s = fma(T[c + (size_t)t * ldt], x[c], s);
+    }
+    y[t] = alpha * s;
+  }
+  __syncthreads();
+}
+
+// Compact-WY append (Sec. 2.4): T(0:kk, kk) = -tau T(0:kk, 0:kk) z, T(kk, kk) = tau
+__device__ void wg_wy_append(double* T, int ldt, int kk, const double* z, double tau) {
+  for (int t = threadIdx.x; t < kk; t += kBT) {
+    double s = 0.0;
+    for (int c = t; c < kk; ++c) s = fma(T[t + (size_t)c * ldt], z[c], s);
+    T[t + (size_t)kk * ldt] = -tau * s;
+  }
+  if (threadIdx.x == 0) T[kk + (size_t)kk * ldt] = tau;
+  __syncthreads();
+}
+
+// Householder reflector of x (length m), LAPACK convention: v[0] = 1,
+// (I - tau v v^T) x = beta e1; x overwritten with (beta, 0, ...) if asked.
+__device__ void wg_house(int m, double* x, double* v, double& tau, double& beta, bool overwrite,
+                         double* sh) {
+  const double alpha = x[0];
+  double amax = 0.0;
+  for (int i = 1 + threadIdx.x; i < m; i += kBT) amax = fmax(amax, fabs(x[i]));
+  amax = block_max(amax, sh);
+  const double sc = safe_scale(fmax(amax, fabs(alpha)));
+  double ss = 0.0;
+  for (int i = 1 + threadIdx.x; i < m; i += kBT) {
+    const double t = x[i] * sc;
+    ss = fma(t, t, ss);
+  }
+  ss = block_sum(ss, sh);
+  const Refl r = make_refl_ss(alpha * sc, ss);
+  const double f = sc * r.scal;
+  tau = r.tau;
+  beta = r.beta / sc;
+  __syncthreads();  // alpha read everywhere before x is overwritten
+  for (int i = 1 + threadIdx.x; i < m; i += kBT) {
+    v[i] = x[i] * f;
+    if (overwrite) x[i] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    v[0] = 1.0;
+    if (overwrite) x[0] = beta;
+  }
+  __syncthreads();
+}
+
+// C(0:m, 0:n) = alpha op(A) op(B) + beta C   (plain loops; C distinct from A, B)
+//   op(A): m x k (A or A^T),  op(B): k x n (B or B^T)
+__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
+                        int lda, const double* B, int ldb, double beta, double* C, int ldc) {
+  for (int c = 0; c < n; ++c) {
+    for (int i = threadIdx.x; i < m; i += kBT) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) {
+        const double a = ta ? A[l + (size_t)i * lda] : A[i + (size_t)l * lda];
+        const double b = tb ? B[c + (size_t)l * ldb] : B[l + (size_t)c * ldb];
+        s = fma(a, b, s);
+      }
+      double* p = C + i + (size_t)c * ldc;
+      *p = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *p);
+    }
+  }
+  __syncthreads();
+}
+
+// y = B(0:m, 0:m) x for upper triangular B; y distinct from x
+__device__ void wg_trmv_upper(int m, const double* B, int ldb, const double* x, double* y) {
+  for (int i = threadIdx.x; i < m; i += kBT) {
+    double s = 0.0;
+    for (int c = i; c < m; ++c) s = fma(B[i + (size_t)c * ldb], x[c], s);
+    y[i] = s;
+  }
+  __syncthreads();
+}
+
+// Scaled back substitution: B(0:m, 0:m) x = 2^{-E} c, returns E >= 0.
+// r (LDS, m doubles) carries the right-hand side and then x; dg (LDS) holds
+// one 64 x 64 diagonal tile.  Wavefront 0 substitutes a 64-row block; any
+// rescaling it needs is then applied to all other entries by everyone.
+__device__ int wg_trsv(int m, const double* B, int ldb, const double* c, double* x, double* r,
+                       double* dg, int* shi) {
+  for (int i = threadIdx.x; i < m; i += kBT) r[i] = c[i];
+  int E = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  for (int b = (m + 63) / 64 - 1; b >= 0; --b) {
+    const int r0 = 64 * b, nr = min(64, m - r0);
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += kBT) {
+      const int rr = idx & 63, cc = idx >> 6;
+      dg[rr + cc * 65] =
+          (rr < nr && cc < nr && rr <= cc) ? B[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ldb] : 0.0;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      const bool live = lane < nr;
+      double rhs = live ? r[r0 + lane] : 0.0;
+      const double d_own = live ? dg[lane * 65 + lane] : 1.0;
+      const double dp = (d_own != 0.0) ? d_own : 1.0;  // zero pivots only when B = 0
+      const double dinv = 1.0 / dp;
+      int shr = 0;
+      for (int rr = nr - 1; rr >= 0; --rr) {
+        double t = readlane_d(rhs, rr);
+        const double dr = readlane_d(dp, rr);
+        int g = 0;
+        while (!(fabs(t) <= kBig * fabs(dr)) && g < 8) {
+          rhs *= kShrink;
+          ++shr;
+          t = readlane_d(rhs, rr);
+          ++g;
+        }
+        const double xr = t * readlane_d(dinv, rr);
+        if (lane == rr) rhs = xr;
+        if (lane < rr) rhs = fma(-dg[rr * 65 + lane], xr, rhs);
+      }
+      if (live) r[r0 + lane] = rhs;
+      if (lane == 0) shi[0] = shr;
+    }
+    __syncthreads();
+    const int shr = shi[0];
+    E += kShrinkExp * shr;
+    // rows below the block (already x) take the rescaling; rows above take it
+    // and the block's products
+    for (int i = r0 + 64 + threadIdx.x; i < m; i += kBT)
+      if (shr) r[i] = ldexp(r[i], -kShrinkExp * shr);
+    for (int i = threadIdx.x; i < r0; i += kBT) {
+      double acc = shr ? ldexp(r[i], -kShrinkExp * shr) : r[i];
+      for (int cc = 0; cc < nr; ++cc) acc = fma(-B[(size_t)i + (size_t)(r0 + cc) * ldb], r[r0 + cc], acc);
+      r[i] = acc;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < m; i += kBT) x[i] = r[i];
+  __syncthreads();
+  return E;
+}
+
+// X(rows, cols) -= (X V) T V^T on the column range of the panel's local
+// frame: X is rows x L (leading dimension ldx), V L x k, T k x k.
+__device__ void wg_right_wy(int rows, int L, int k, double* X, int ldx, const double* V,
+                            const double* T, const BWork& w) {
+  if (rows <= 0 || k <= 0) return;
+  wg_gemm(false, false, rows, k, L, 1.0, X, ldx, V, w.ld, 0.0, w.P, w.ld);
+  wg_gemm(false, false, rows, k, k, 1.0, w.P, w.ld, T, w.ld, 0.0, w.P2, w.ld);
+  wg_gemm(false, true, rows, L, k, -1.0, w.P2, w.ld, V, w.ld, 1.0, X, ldx);
+}
+// X(0:L, cols) -= U S^T (U^T X): X is L x ncols
+__device__ void wg_left_wy(int L, int ncols, int k, double* X, int ldx, const double* U,
+                           const double* S, const BWork& w) {
+  if (ncols <= 0 || k <= 0) return;
+  wg_gemm(true, false, k, ncols, L, 1.0, U, w.ld, X, ldx, 0.0, w.P, w.ld);
+  wg_gemm(true, false, k, ncols, k, 1.0, S, w.ld, w.P, w.ld, 0.0, w.P2, w.ld);
+  wg_gemm(false, false, L, ncols, k, -1.0, U, w.ld, w.P2, w.ld, 1.0, X, ldx);
+}
+
+struct Pencil {
+  int n, ld;
+  double *A, *B, *Q, *Z;
+};
+
+// Factored solve (Sec. 3.2.2 c): ctil <- (I - U S U^T) ctil (nu reflectors),
+// B(s+1:n, s+1:n) ysol = 2^{-E} ctil, ysol <- (I - V T^T V^T) ysol (kk).
+__device__ int factored_solve(const Pencil& P, const BWork& w, int s, int kk, int nu, double* ctil,
+                              double* ysol, double* r, double* dg, int* shi) {
+  const int L = P.n - s - 1;
+  wg_gemv_t(L, nu, 1.0, w.U, w.ld, ctil, 0.0, w.tk);
+  wg_trmv_small(false, nu, w.S, w.ld, w.tk, 1.0, w.tk2);
+  wg_gemv_n(L, nu, -1.0, w.U, w.ld, w.tk2, 1, 1.0, ctil);
+  const double* Bp = P.B + (size_t)(s + 1) + (size_t)(s + 1) * P.ld;
+  const int E = wg_trsv(L, Bp, P.ld, ctil, ysol, r, dg, shi);
+  if (kk > 0) {
+    wg_gemv_t(L, kk, 1.0, w.V, w.ld, ysol, 0.0, w.tk);
+    wg_trmv_small(true, kk, w.T, w.ld, w.tk, 1.0, w.tk2);
+    wg_gemv_n(L, kk, -1.0, w.V, w.ld, w.tk2, 1, 1.0, ysol);
+  }
+  return E;
+}
+
+// Residual of the refined solve (Sec. 3.2.2 c): w = (I - V T V^T)[0; x],
+// w = B w, w = (I - U S^T U^T) w, r = 2^{-E} e1 - w(kk:); returns whether
+// ||r|| <= tol_factor u ||B||_F ||x||.
+__device__ bool residual(const Pencil& P, const BWork& w, int s, int kk, const double* x, int E,
+                         double normB, double tol_factor, double* sh) {
+  const int L = P.n - s - 1, m = L - kk;
+  for (int i = threadIdx.x; i < L; i += kBT) w.wv[i] = (i < kk) ? 0.0 : x[i - kk];
+  __syncthreads();
+  wg_gemv_t(m, kk, 1.0, w.V + kk, w.ld, x, 0.0, w.tk);
+  wg_trmv_small(false, kk, w.T, w.ld, w.tk, 1.0, w.tk2);
+  wg_gemv_n(L, kk, -1.0, w.V, w.ld, w.tk2, 1, 1.0, w.wv);
+  const double* Bp = P.B + (size_t)(s + 1) + (size_t)(s + 1) * P.ld;
+  wg_trmv_upper(L, Bp, P.ld, w.wv, w.w2);
+  wg_gemv_t(L, kk + 1, 1.0, w.U, w.ld, w.w2, 0.0, w.tk);
+  wg_trmv_small(true, kk + 1, w.S, w.ld, w.tk, 1.0, w.tk2);
+  wg_gemv_n(L, kk + 1, -1.0, w.U, w.ld, w.tk2, 1, 1.0, w.w2);
+  double rmax = 0.0, xmax = 0.0;
+  for (int i = threadIdx.x; i < m; i += kBT) {
+    const double ri = ldexp(i == 0 ? 1.0 : 0.0, -E) - w.w2[kk + i];
+    w.rv[i] = ri;
+    rmax = fmax(rmax, fabs(ri));
+    xmax = fmax(xmax, fabs(x[i]));
+  }
+  rmax = block_max(rmax, sh);
+  xmax = block_max(xmax, sh);
+  const double ir = safe_scale(rmax), ix = safe_scale(xmax);
+  double rs = 0.0, xs = 0.0;
+  for (int i = threadIdx.x; i < m; i += kBT) {
+    const double a = w.rv[i] * ir, b = x[i] * ix;
+    rs = fma(a, a, rs);
+    xs = fma(b, b, xs);
+  }
+  rs = block_sum(rs, sh);
+  xs = block_sum(xs, sh);
+  const double rn = sqrt(rs) / ir, xn = sqrt(xs) / ix;
+  return rn <= tol_factor * kUnitRoundoff * normB * xn;
+}
+
+// Householder QR of B(c0:n, c0:n) (restores a triangular trailing block);
+// each reflector is applied to B(c:n, c+1:n), A(c:n, a0:n) and Q(:, c:n).
+__device__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0, double* sh) {
+  const int n = P.n, ld = P.ld;
+  for (int c = c0; c < n - 1; ++c) {
+    const int m = n - c;
+    double* col = P.B + (size_t)c + (size_t)c * ld;
+    double tau, beta;
+    wg_house(m, col, w.acol, tau, beta, true, sh);
+    if (tau == 0.0) continue;
+    // X(c:n, cols) -= tau v (v^T X)
+    auto left = [&](double* X, int ncols) {
+      for (int cc = threadIdx.x; cc < ncols; cc += kBT) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s = fma(w.acol[i], X[i + (size_t)cc * ld], s);
+        s *= tau;
+        for (int i = 0; i < m; ++i) X[i + (size_t)cc * ld] = fma(-s, w.acol[i], X[i + (size_t)cc * ld]);
+      }
+      __syncthreads();
+    };
+    left(P.B + (size_t)c + (size_t)(c + 1) * ld, n - c - 1);
+    left(P.A + (size_t)c + (size_t)a0 * ld, n - a0);
+    // Q(:, c:n) -= tau (Q v) v^T
+    for (int i = threadIdx.x; i < n; i += kBT) {
+      double s = 0.0;
+      for (int l = 0; l < m; ++l) s = fma(P.Q[i + (size_t)(c + l) * ld], w.acol[l], s);
+      s *= tau;
+      for (int l = 0; l < m; ++l)
+        P.Q[i + (size_t)(c + l) * ld] = fma(-s, w.acol[l], P.Q[i + (size_t)(c + l) * ld]);
+    }
+    __syncthreads();
+  }
+}
+
+// Absorb the k reflector pairs of the panel starting at column s; columns
+// s..j-1 (j = s+k) are reduced, columns j..n-1 still carry the pending
+// updates.  failed: the panel ended at column j by a refinement failure.
+__device__ void absorb_dense(const Pencil& P, const BWork& w, int s, int k, bool failed,
+                             double* sh) {
+  const int n = P.n, ld = P.ld, L = n - s - 1, j = s + k;
+  if (k > 0) {
+    // A: rows 0..s take the right transformation on columns s+1..n-1; rows
+    // s+1.. of the unreduced columns j..n-1 take the column update (a)
+    wg_right_wy(s + 1, L, k, P.A + (size_t)(s + 1) * ld, ld, w.V, w.T, w);
+    double* Aj = P.A + (size_t)(s + 1) + (size_t)j * ld;
+    wg_gemm(false, true, L, n - j, k, -1.0, w.Y, w.ld, w.V + (j - s - 1), w.ld, 1.0, Aj, ld);
+    wg_left_wy(L, n - j, k, Aj, ld, w.U, w.S, w);
+    // B: (I - U S^T U^T) B (I - V T V^T) on rows/columns s+1..n-1 (rows
+    // 0..s only from the right)
+    wg_right_wy(n, L, k, P.B + (size_t)(s + 1) * ld, ld, w.V, w.T, w);
+    wg_left_wy(L, L, k, P.B + (size_t)(s + 1) + (size_t)(s + 1) * ld, ld, w.U, w.S, w);
+    // Q <- Q (I - U S U^T), Z <- Z (I - V T V^T) on columns s+1..n-1
+    {
+      double* X = P.Q + (size_t)(s + 1) * ld;
+      wg_gemm(false, false, n, k, L, 1.0, X, ld, w.U, w.ld, 0.0, w.P, w.ld);
+      wg_gemm(false, false, n, k, k, 1.0, w.P, w.ld, w.S, w.ld, 0.0, w.P2, w.ld);
+      wg_gemm(false, true, n, L, k, -1.0, w.P2, w.ld, w.U, w.ld, 1.0, X, ld);
+    }
+    wg_right_wy(n, L, k, P.Z + (size_t)(s + 1) * ld, ld, w.V, w.T, w);
+  }
+  // reduced columns of B: the entries below the diagonal are rounding noise
+  // of the opposite reflectors (Lemma 2.1)
+  const int clast = failed ? j : n - 1;
+  for (int c = s + 1; c <= clast && c < n; ++c)
+    for (int i = c + 1 + threadIdx.x; i < n; i += kBT) P.B[i + (size_t)c * ld] = 0.0;
+  __syncthreads();
+  if (failed) retriangularise(P, w, j + 1, j, sh);
+}
+
+__device__ void reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& w, uint64_t seed,
+                              double* r, double* dg, int* shi, double* sh) {
+  const int n = P.n, ld = P.ld;
+  // Q = Z = I; B's strict lower triangle ignored on entry
+  for (int c = 0; c < n; ++c)
+    for (int i = threadIdx.x; i < n; i += kBT) {
+      P.Q[i + (size_t)c * ld] = (i == c) ? 1.0 : 0.0;
+      P.Z[i + (size_t)c * ld] = (i == c) ? 1.0 : 0.0;
+      if (i > c) P.B[i + (size_t)c * ld] = 0.0;
+    }
+  __syncthreads();
+  // ||B||_F with a power-of-two scaling
+  double bmax = 0.0;
+  for (int c = 0; c < n; ++c)
+    for (int i = threadIdx.x; i <= c; i += kBT) bmax = fmax(bmax, fabs(P.B[i + (size_t)c * ld]));
+  bmax = block_max(bmax, sh);
+  const double bsc = safe_scale(bmax);
+  double bss = 0.0;
+  for (int c = 0; c < n; ++c)
+    for (int i = threadIdx.x; i <= c; i += kBT) {
+      const double t = P.B[i + (size_t)c * ld] * bsc;
+      bss = fma(t, t, bss);
+    }
+  bss = block_sum(bss, sh);
+  const double normB = sqrt(bss) / bsc;
+  if (n <= 2) return;
+
+  int s = 0;
+  uint64_t panel = 0;
+  while (s <= n - 3) {
+    const int L = n - s - 1;
+    const int kmax = n - 2 - s;
+    // zero-diagonal rule (Remark 2.2) for the trailing diagonal
+    if (normB > 0.0) {
+      for (int i = s + 1 + threadIdx.x; i < n; i += kBT) {
+        double* p = P.B + (size_t)i + (size_t)i * ld;
+        if (fabs(*p) < 2.2250738585072014e-308) {
+          double rho = normal_draw(seed, (panel + 1) * (uint64_t)n + (uint64_t)i);
+          if (rho == 0.0) rho = 1.0;
+          *p = 2.0 * kUnitRoundoff * rho * normB;
+        }
+      }
+    }
+    wg_zero_mat(w.U, L, kmax + 1, w.ld);
+    wg_zero_mat(w.V, L, kmax, w.ld);
+    wg_zero_mat(w.S, kmax + 1, kmax + 1, w.ld);
+    wg_zero_mat(w.T, kmax, kmax, w.ld);
+    int k = 0;
+    bool failed = false;
+    for (int kk = 0; kk < kmax; ++kk) {
+      const int j = s + kk;
+      double* acol = P.A + (size_t)(s + 1) + (size_t)j * ld;
+      wg_copy(w.acol, acol, L);
+      // (a) column update with the kk pending pairs
+      if (kk > 0) {
+        wg_gemv_n(L, kk, -1.0, w.Y, w.ld, w.V + (kk - 1), w.ld, 1.0, acol);
+        wg_gemv_t(L, kk, 1.0, w.U, w.ld, acol, 0.0, w.tk);
+        wg_trmv_small(true, kk, w.S, w.ld, w.tk, 1.0, w.tk2);
+        wg_gemv_n(L, kk, -1.0, w.U, w.ld, w.tk2, 1, 1.0, acol);
+      }
+      // (b) left reflector, S
+      const int m = L - kk;
+      double* ucol = w.U + kk + (size_t)kk * w.ld;
+      double tau_u, beta_u;
+      wg_house(m, acol + kk, ucol, tau_u, beta_u, true, sh);
+      if (kk > 0) wg_gemv_t(m, kk, 1.0, w.U + kk, w.ld, ucol, 0.0, w.tk);
+      wg_wy_append(w.S, w.ld, kk, w.tk, tau_u);
+      // (c) solve, with refinement from the second column on
+      wg_fill(w.ctil, L, 0.0);
+      if (threadIdx.x == 0) w.ctil[kk] = 1.0;
+      __syncthreads();
+      int E = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.ysol, r, dg, shi);
+      double* x = w.ysol + kk;
+      bool ok = true;
+      if (kk > 0) {
+        bool st = residual(P, w, s, kk, x, E, normB, a.tol_factor, sh);
+        for (int it = 0; !st && it < a.max_ir; ++it) {
+          for (int i = threadIdx.x; i < L; i += kBT) w.ctil[i] = (i < kk) ? 0.0 : w.rv[i - kk];
+          __syncthreads();
+          const int E2 = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.dsol, r, dg, shi);
+          for (int i = threadIdx.x; i < m; i += kBT) x[i] = ldexp(x[i], -E2) + w.dsol[kk + i];
+          __syncthreads();
+          E += E2;
+          st = residual(P, w, s, kk, x, E, normB, a.tol_factor, sh);
+        }
+        ok = st;
+      }
+      if (!ok) {
+        wg_copy(acol, w.acol, L);  // undo (a) and (b) on column j
+        failed = true;
+        break;
+      }
+      // (d) opposite reflector, T, Y column
+      double* vcol = w.V + kk + (size_t)kk * w.ld;
+      double tau_v, beta_v;
+      wg_house(m, x, vcol, tau_v, beta_v, false, sh);
+      if (kk > 0) wg_gemv_t(m, kk, 1.0, w.V + kk, w.ld, vcol, 0.0, w.tk);
+      wg_wy_append(w.T, w.ld, kk, w.tk, tau_v);
+      double* ycol = w.Y + (size_t)kk * w.ld;
+      wg_gemv_n(L, m, 1.0, P.A + (size_t)(s + 1) + (size_t)(j + 1) * ld, ld, vcol, 1, 0.0, ycol);
+      if (kk > 0) wg_gemv_n(L, kk, -1.0, w.Y, w.ld, w.tk, 1, 1.0, ycol);
+      for (int i = threadIdx.x; i < L; i += kBT) ycol[i] *= tau_v;
+      __syncthreads();
+      k = kk + 1;
+    }
+    absorb_dense(P, w, s, k, failed, sh);
+    s += k;
+    ++panel;
+  }
+}
+
+// Counting sort of the pencils by decreasing order; resets the ticket.
+__global__ __launch_bounds__(1024) void k_batched_order(BatchArgs a) {
+  __shared__ int cnt[kBMax + 2];
+  for (int i = threadIdx.x; i < kBMax + 2; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  auto bin = [&](int i) {
+    const int nn = min(max(a.n[i], 0), kBMax + 1);
+    return kBMax + 1 - nn;
+  };
+  for (int i = threadIdx.x; i < a.batch; i += blockDim.x) atomicAdd(&cnt[bin(i)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int b = 0; b < kBMax + 2; ++b) {
+      const int c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.batch; i += blockDim.x) a.order[atomicAdd(&cnt[bin(i)], 1)] = i;
+  if (threadIdx.x == 0) a.counter[0] = 0;
+}
+
+__global__ __launch_bounds__(kBT) void k_batched(BatchArgs a) {
+  __shared__ double r[kBMax];
+  __shared__ double dg[64 * 65];
+  __shared__ double sh[kBNW];
+  __shared__ int shi[2];
+  const BWork w = bwork(a.scratch + (size_t)blockIdx.x * a.scratch_stride, a.nmax);
+  for (;;) {
+    if (threadIdx.x == 0) shi[1] = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int t = shi[1];
+    __syncthreads();
+    if (t >= a.batch) break;
+    const int pi = a.order[t];
+    Pencil P;
+    P.n = a.n[pi];
+    P.ld = a.ld[pi];
+    P.A = a.A[pi];
+    P.B = a.B[pi];
+    P.Q = a.Q[pi];
+    P.Z = a.Z[pi];
+    int info = 0;
+    if (P.n < 0 || P.n > a.nmax || P.ld < max(1, P.n) ||
+        (P.n > 0 && (!P.A || !P.B || !P.Q || !P.Z)))
+      info = -1;
+    else
+      reduce_pencil(a, P, w, a.seed ^ splitmix64((uint64_t)pi + 1), r, dg, shi, sh);
+    if (threadIdx.x == 0) a.info[pi] = info;
+    __syncthreads();
+  }
+}
+
+size_t batch_grid(int batch) { return (size_t)std::max(1, std::min(batch, 2 * num_cus())); }
+size_t batch_stride(int nmax) {
+  const size_t d = 7 * (size_t)nmax * nmax + 9 * (size_t)nmax;
+  return (d * 8 + 255) / 256 * 32;  // doubles, rounded to 256 bytes
+}
+
+}  // namespace
+
+size_t batched_workspace_bytes(int batch, int nmax) {
+  if (batch <= 0) return 256;
+  return 256 + ((size_t)batch * 4 + 255) / 256 * 256 + batch_grid(batch) * batch_stride(nmax) * 8;
+}
+
+int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* const* A_dev,
+                   double* const* B_dev, double* const* Q_dev, double* const* Z_dev,
+                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int max_ir,
+                   double tol_factor, uint64_t seed, void* workspace) {
+  if (batch <= 0) return 0;
+  char* base = (char*)workspace;
+  BatchArgs a;
+  a.batch = batch;
+  a.nmax = std::max(nmax, 1);
+  a.max_ir = max_ir;
+  a.n = n_dev;
+  a.A = A_dev;
+  a.B = B_dev;
+  a.Q = Q_dev;
+  a.Z = Z_dev;
+  a.ld = ld_dev;
+  a.info = info_dev;
+  a.counter = (int*)base;
+  a.order = (int*)(base + 256);
+  a.scratch = (double*)(base + 256 + ((size_t)batch * 4 + 255) / 256 * 256);
+  a.scratch_stride = batch_stride(a.nmax);
+  a.tol_factor = tol_factor;
+  a.seed = seed;
+  hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(k_batched, dim3((unsigned)batch_grid(batch)), dim3(kBT), 0, st, a);
+  return 0;
+}
+
+}  // namespace htk

@@ -823,17 +823,35 @@ const char* ht_strerror(int code) {
 const char* ht_version(void) { return "htred 0.1 gfx950"; }
 
 size_t ht_batched_workspace_size(int32_t batch, int32_t nmax, const ht_options* opt) {
-  (void)batch; (void)nmax; (void)opt;
-  return 0;
+  ht_options o;
+  if (resolve_opts(opt, &o) != 0 || batch < 0 || nmax < 0 || nmax > 512) return 0;
+  return batched_workspace_bytes(batch, std::max(nmax, 1)) + 256;
 }
 
 int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
                       double* const* B_dev, double* const* Q_dev, double* const* Z_dev,
                       const int32_t* ld_dev, int32_t* info_dev, int32_t nmax,
                       const ht_options* opt, void* workspace, size_t ws_bytes, void* stream) {
-  (void)batch; (void)n_dev; (void)A_dev; (void)B_dev; (void)Q_dev; (void)Z_dev; (void)ld_dev;
-  (void)info_dev; (void)nmax; (void)opt; (void)workspace; (void)ws_bytes; (void)stream;
-  return HT_ERR_UNSUPPORTED;
+  if (batch < 0) return -1;
+  if (batch == 0) return HT_OK;
+  if (!n_dev) return -2;
+  if (!A_dev || !B_dev) return -3;
+  if (!Q_dev || !Z_dev) return -5;
+  if (!ld_dev) return -7;
+  if (!info_dev) return -8;
+  if (nmax < 0 || nmax > 512) return -9;
+  ht_options o;
+  const int rc = resolve_opts(opt, &o);
+  if (rc != 0) return rc;
+  if (o.prec != HT_PREC_FP64) return HT_ERR_UNSUPPORTED;
+  if (!workspace || ((uintptr_t)workspace & 255) ||
+      ws_bytes < batched_workspace_bytes(batch, std::max(nmax, 1)))
+    return HT_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  batched_reduce(st, batch, n_dev, A_dev, B_dev, Q_dev, Z_dev, ld_dev, info_dev,
+                 std::max(nmax, 1), o.max_ir, o.ir_tol_factor, o.seed, workspace);
+  if (hipGetLastError() != hipSuccess) return HT_ERR_HIP;
+  return HT_OK;
 }
 
 }  // extern "C"

@@ -159,6 +159,62 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     return Q, Z
 
 
+class BatchedPlan:
+    """Device-side argument arrays and workspace for ht_reduce_batched over a
+    fixed list of column-major pencils (A_i, B_i, Q_i, Z_i share ld_i).  The
+    arrays stay alive with the plan, so `run` may be captured in a hipGraph."""
+
+    def __init__(self, As, Bs, Qs, Zs, max_ir=10, ir_tol_factor=2.0, seed=0x5EED):
+        dev = As[0].device if As else torch.device("cuda")
+        self.batch = len(As)
+        ns, lds = [], []
+        for A, B, Q, Z in zip(As, Bs, Qs, Zs):
+            n = A.shape[0]
+            ld = _ld(A, n, "A")
+            for M, name in ((B, "B"), (Q, "Q"), (Z, "Z")):
+                if M.shape[0] != n or _ld(M, n, name) != ld:
+                    raise ValueError("pencil matrices must share order and leading dimension")
+            ns.append(n)
+            lds.append(ld)
+        self.nmax = max(ns) if ns else 0
+        i32 = dict(dtype=torch.int32, device=dev)
+        i64 = dict(dtype=torch.int64, device=dev)
+        self.n = torch.tensor(ns, **i32)
+        self.ld = torch.tensor(lds, **i32)
+        self.pA = torch.tensor([t.data_ptr() for t in As], **i64)
+        self.pB = torch.tensor([t.data_ptr() for t in Bs], **i64)
+        self.pQ = torch.tensor([t.data_ptr() for t in Qs], **i64)
+        self.pZ = torch.tensor([t.data_ptr() for t in Zs], **i64)
+        self.info = torch.zeros(max(self.batch, 1), **i32)
+        self.opt = options(max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed)
+        nbytes = lib().ht_batched_workspace_size(self.batch, self.nmax, ctypes.byref(self.opt))
+        if nbytes == 0:
+            raise HTError("invalid batched sizes (orders must be <= 512)")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.keep = (As, Bs, Qs, Zs)
+
+    def run(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        rc = lib().ht_reduce_batched(self.batch, self.n.data_ptr(), self.pA.data_ptr(),
+                                     self.pB.data_ptr(), self.pQ.data_ptr(), self.pZ.data_ptr(),
+                                     self.ld.data_ptr(), self.info.data_ptr(), self.nmax,
+                                     ctypes.byref(self.opt), self.ws.data_ptr(),
+                                     self.ws.numel(), s.cuda_stream)
+        _check(rc)
+
+
+def reduce_batched(As, Bs, Qs=None, Zs=None, **kw):
+    """Batched HouseHT of small pencils (orders <= 512) in one persistent launch:
+    A_i -> H_i, B_i -> T_i in place; returns (Qs, Zs, info)."""
+    if Qs is None:
+        Qs = [colmajor_empty(A.shape[0], device=A.device) for A in As]
+    if Zs is None:
+        Zs = [colmajor_empty(A.shape[0], device=A.device) for A in As]
+    plan = BatchedPlan(As, Bs, Qs, Zs, **kw)
+    plan.run()
+    return Qs, Zs, plan.info[:len(As)].clone()
+
+
 def workspace_size(n, nb=64):
     return lib().ht_workspace_size(n, ctypes.byref(options(nb=nb)))
 

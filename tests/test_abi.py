@@ -73,3 +73,16 @@ def test_strerror(L):
     assert L.ht_strerror(0) == b"success"
     assert b"argument" in L.ht_strerror(-3)
     assert L.ht_version().startswith(b"htred")
+
+
+def test_batched_argument_validation(L):
+    from paper_1710_08538_amd import htred
+    o = htred.options()
+    assert L.ht_batched_workspace_size(4, 513, ctypes.byref(o)) == 0
+    assert L.ht_batched_workspace_size(4, 64, ctypes.byref(o)) > 0
+    assert L.ht_reduce_batched(-1, None, None, None, None, None, None, None, 64,
+                               ctypes.byref(o), None, 0, None) == -1
+    assert L.ht_reduce_batched(0, None, None, None, None, None, None, None, 64,
+                               ctypes.byref(o), None, 0, None) == 0
+    assert L.ht_reduce_batched(3, None, None, None, None, None, None, None, 64,
+                               ctypes.byref(o), None, 0, None) == -2

@@ -1,0 +1,146 @@
+"""GPU parity of the batched form (ht_reduce_batched through the C ABI):
+many small pencils reduced in one persistent launch, each compared with the
+CPU oracle after sign normalisation (tolerance 1e-10) and checked against the
+invariants (exact zeros, orthogonality <= 1e-13 n, backward error <= 1e-14 n)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import checks
+from paper_1710_08538_amd import htred, inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def to_dev(pencils):
+    As = [htred.to_device_colmajor(A) for A, _ in pencils]
+    Bs = [htred.to_device_colmajor(B) for _, B in pencils]
+    return As, Bs
+
+
+def run_batched(pencils, **kw):
+    print("ht_reduce_batched sizes=%s %s" % ([A.shape[0] for A, _ in pencils], kw), flush=True)
+    As, Bs = to_dev(pencils)
+    Qs, Zs, info = htred.reduce_batched(As, Bs, **kw)
+    torch.cuda.synchronize()
+    outs = [tuple(M.cpu().numpy() for M in (As[i], Bs[i], Qs[i], Zs[i])) for i in range(len(As))]
+    return outs, info.cpu().numpy()
+
+
+def check_pencil(A0, B0, got, ref=None, upto=None):
+    n = A0.shape[0]
+    inv = checks.invariants(A0, B0, *got)
+    assert checks.invariants_ok(inv, n), (n, inv)
+    if ref is not None:
+        d = checks.compare(ref, got, A0, B0, upto=upto)
+        for key in ("max_H", "max_T", "max_Q", "max_Z"):
+            assert d[key] <= TOL, (n, key, d)
+
+
+def test_batched_parity_mixed_orders():
+    sizes = [3, 4, 5, 7, 9, 16, 17, 31, 33, 40, 64, 65, 80, 100, 127, 130]
+    pencils = [inputs.random_pencil(n, seed=500 + n) for n in sizes]
+    outs, info = run_batched(pencils)
+    assert (info == 0).all()
+    for (A0, B0), got in zip(pencils, outs):
+        check_pencil(A0, B0, got, oracle.basic_ht(A0, B0)[:4])
+
+
+def test_batched_edge_orders():
+    sizes = [0, 1, 2, 3, 2, 1]
+    pencils = [inputs.random_pencil(n, seed=40 + i) for i, n in enumerate(sizes)]
+    outs, info = run_batched(pencils)
+    assert (info == 0).all()
+    for (A0, B0), (H, T, Q, Z) in zip(pencils, outs):
+        n = A0.shape[0]
+        if n <= 2:
+            assert np.array_equal(Q, np.eye(n)) and np.array_equal(Z, np.eye(n))
+            assert np.array_equal(H, A0) and np.array_equal(T, np.triu(B0))
+        else:
+            check_pencil(A0, B0, (H, T, Q, Z), oracle.basic_ht(A0, B0)[:4])
+
+
+def test_batched_workload_sample():
+    """Pencils of the batched workload's own distribution (orders U{32..512},
+    child seeds of SeedSequence(4)); parity with Moler-Stewart."""
+    count = 2048
+    sizes = inputs.batch_sizes(count, 4)
+    idx = list(range(0, count, 97))[:20]
+    pencils = [inputs.batch_pencil(i, sizes[i], count, 4) for i in idx]
+    outs, info = run_batched(pencils)
+    assert (info == 0).all()
+    for (A0, B0), got in zip(pencils, outs):
+        check_pencil(A0, B0, got, oracle.ms_ht(A0, B0)[:4])
+
+
+def test_batched_largest_orders():
+    pencils = [inputs.random_pencil(512, seed=61), inputs.random_pencil(511, seed=62),
+               inputs.random_pencil(300, seed=63)]
+    outs, info = run_batched(pencils)
+    assert (info == 0).all()
+    for (A0, B0), got in zip(pencils, outs):
+        check_pencil(A0, B0, got, oracle.ms_ht(A0, B0, ncols=10)[:4], upto=10)
+
+
+def test_batched_forced_refinement_failures():
+    """max_ir = 0 and a zero tolerance: every column after the first of each
+    panel fails, so each panel absorbs one pair and re-triangularises B."""
+    pencils = [inputs.random_pencil(n, seed=70 + n) for n in (12, 25, 40)]
+    outs, info = run_batched(pencils, max_ir=0, ir_tol_factor=0.0)
+    assert (info == 0).all()
+    for (A0, B0), got in zip(pencils, outs):
+        check_pencil(A0, B0, got, oracle.basic_ht(A0, B0)[:4])
+
+
+def test_batched_illconditioned():
+    pencils = [inputs.illcond_pencil(n, seed=80 + n) for n in (64, 150, 200)]
+    outs, info = run_batched(pencils)
+    assert (info == 0).all()
+    for (A0, B0), got in zip(pencils, outs):
+        assert all(np.isfinite(M).all() for M in got)
+        check_pencil(A0, B0, got)
+
+
+def test_batched_graph_capture_replays():
+    """The batched call captured in a hipGraph: every replay (inputs restored
+    eagerly in between) equals the eager run bit for bit."""
+    sizes = [20, 45, 70, 33, 96]
+    pencils = [inputs.random_pencil(n, seed=90 + n) for n in sizes]
+    A0s, B0s = to_dev(pencils)
+    As = [A.clone() for A in A0s]
+    Bs = [B.clone() for B in B0s]
+    Qs = [htred.colmajor_empty(A.shape[0]) for A in As]
+    Zs = [htred.colmajor_empty(A.shape[0]) for A in As]
+    # column-major clones
+    for i in range(len(As)):
+        As[i] = htred.to_device_colmajor(A0s[i]); Bs[i] = htred.to_device_colmajor(B0s[i])
+    plan = htred.BatchedPlan(As, Bs, Qs, Zs)
+    plan.run()
+    torch.cuda.synchronize()
+    ref = [tuple(M.clone() for M in (As[i], Bs[i], Qs[i], Zs[i])) for i in range(len(As))]
+
+    def restore():
+        for i in range(len(As)):
+            As[i].copy_(A0s[i]); Bs[i].copy_(B0s[i])
+
+    g = torch.cuda.CUDAGraph()
+    restore()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.run(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        restore()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(len(As)):
+            for M, R in zip((As[i], Bs[i], Qs[i], Zs[i]), ref[i]):
+                assert torch.equal(M, R), (rep, i)
+    assert (plan.info.cpu().numpy()[:len(As)] == 0).all()
