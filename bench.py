@@ -68,6 +68,8 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
     """The batched workload: `count` pencils with orders U{32..512} (child seeds
     of SeedSequence(seed)), reduced in one persistent launch; timed eagerly and
     as a hipGraph replay, inputs restored from device copies before each run."""
+    import numpy as np
+
     sizes = inputs.batch_sizes(count, seed)
     pencils = inputs.batch_pencils(count, seed)
     A0s = [htred.to_device_colmajor(A) for A, _ in pencils]
@@ -92,6 +94,9 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
     plan.run()
     torch.cuda.synchronize()
     eager_s = time.time() - t
+    ps = plan.pencil_stats().numpy()
+    lat_ms = (ps[:, 1] - ps[:, 0]) / 1e6
+    big = np.asarray(sizes) >= 480
     g = torch.cuda.CUDAGraph()
     st = torch.cuda.Stream()
     restore()
@@ -118,6 +123,14 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
     return {"pencils": count, "orders": "U{32..512}", "seed": seed,
             "ms": 1000.0 * eager_s, "pencils_per_s": count / eager_s,
             "gflops_nominal": fl / eager_s / 1e9, "graph_replay_ms": 1000.0 * graph_s,
+            "latency_ms_p50": float(np.percentile(lat_ms, 50)),
+            "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+            "latency_ms_mean_n_ge_480": float(lat_ms[big].mean()) if big.any() else None,
+            "device_span_ms": float(ps[:, 1].max() / 1e6),
+            "panels_total": int(ps[:, 2].sum()), "ir_steps_total": int(ps[:, 3].sum()),
+            "phase_share_n_ge_480": ({k: float(ps[big, c].sum() / (ps[big, 1] - ps[big, 0]).sum())
+                                      for k, c in (("solve", 4), ("residual", 5), ("absorb", 6))}
+                                     if big.any() else None),
             "checked_sample": len(range(0, count, 32)), "invariants_ok": ok,
             "backward_error_max": worst}
 

@@ -167,6 +167,22 @@ int ht_reduce_batched(int32_t batch, const int32_t *n_dev,
                       const ht_options *opt, void *workspace, size_t ws_bytes,
                       void *stream);
 
+/*
+ * ht_batched_pencil_stats -- per-pencil record of the last ht_reduce_batched
+ * call that used `workspace` (same batch): waits for `stream`, then writes
+ * out[8 i + 0..7] (host array of 8*batch int64) for pencil i:
+ *   0, 1  start and end in nanoseconds of the device wall clock, relative
+ *         to the earliest start in the batch;
+ *   2     number of panels (absorptions) of its reduction;
+ *   3     number of iterative-refinement steps (Sec. 3.2.2);
+ *   4, 5, 6  nanoseconds spent in the factored solves, in the residuals and
+ *         in the absorptions;
+ *   7     reserved (0).
+ * Returns -1 for a NULL workspace, -2 for batch < 0, -3 for a NULL out,
+ * HT_ERR_HIP if the copy fails.  Meaningless before the batched call ran.
+ */
+int ht_batched_pencil_stats(const void *workspace, int32_t batch, int64_t *out, void *stream);
+
 /* Human-readable name of a return code. */
 const char *ht_strerror(int code);
 

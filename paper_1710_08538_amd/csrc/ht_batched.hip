@@ -37,6 +37,7 @@ namespace {
 constexpr int kBT = 256;  // threads per pencil workgroup
 constexpr int kBNW = kBT / 64;
 constexpr int kBMax = 512;
+constexpr int kStatWords = 8;
 
 struct BatchArgs {
   int batch, nmax, max_ir;
@@ -49,6 +50,7 @@ struct BatchArgs {
   int32_t* info;
   int* counter;
   int* order;
+  int64_t* stats;       // per pencil: kStatWords words (see k_batched)
   double* scratch;      // per workgroup: scratch_stride doubles
   size_t scratch_stride;
   double tol_factor;
@@ -91,74 +93,167 @@ __device__ BWork bwork(double* base, int nmax) {
 // global-memory results are visible to the whole workgroup.
 // ---------------------------------------------------------------------------
 
-__device__ void wg_fill(double* x, int m, double v) {
+__device__ __noinline__ void wg_fill(double* x, int m, double v) {
   for (int i = threadIdx.x; i < m; i += kBT) x[i] = v;
   __syncthreads();
 }
-__device__ void wg_copy(double* y, const double* x, int m) {
+__device__ __noinline__ void wg_copy(double* y, const double* x, int m) {
   for (int i = threadIdx.x; i < m; i += kBT) y[i] = x[i];
   __syncthreads();
 }
-__device__ void wg_zero_mat(double* X, int m, int n, int ld) {
+__device__ __noinline__ void wg_zero_mat(double* X, int m, int n, int ld) {
   for (int c = 0; c < n; ++c)
     for (int i = threadIdx.x; i < m; i += kBT) X[i + (size_t)c * ld] = 0.0;
   __syncthreads();
 }
 
+// LDS staging area of the pencil workgroup: a vector of up to kBMax entries
+// and a block that holds either 4 columns of an operand (kBMax x 4) or the
+// 64 x 64 diagonal tile of a triangular solve (leading dimension 65).
+constexpr int kTileLd = 65;
+struct Lds {
+  double xs[kBMax];
+  double bs[64 * kTileLd];
+};
+
+__device__ void stage_vec(double* xs, const double* x, int k, int incx) {
+  for (int c = threadIdx.x; c < k; c += kBT) xs[c] = x[(size_t)c * incx];
+  __syncthreads();
+}
+
+// Dot product of a strided global row segment with an LDS vector, sixteen
+// independent accumulators so that sixteen loads are in flight at a time
+// (the pencil workgroups are latency-bound, not bandwidth-bound).
+__device__ __forceinline__ double row_dot(const double* X, size_t ldx, const double* xs, int c0,
+                                          int c1) {
+  double s[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s[u] = 0.0;
+  int c = c0;
+  for (; c + 16 <= c1; c += 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s[u] = fma(X[(size_t)(c + u) * ldx], xs[c + u], s[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < 15; ++u)
+    if (c + u < c1) s[u] = fma(X[(size_t)(c + u) * ldx], xs[c + u], s[u]);
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) s[u] += s[u + h];
+  return s[0];
+}
+
+// Sums eight per-lane values over the wavefront in ten exchanges (a
+// butterfly that halves the number of values per lane at each of the first
+// three stages); lane l receives the total of value (l >> 3) & 7.
+__device__ __forceinline__ double wave_sum8(const double (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double a[4], b[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    a[j] = (h5 ? v[j + 4] : v[j]) + __shfl_xor(h5 ? v[j] : v[j + 4], 32, 64);
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    b[j] = (h4 ? a[j + 2] : a[j]) + __shfl_xor(h4 ? a[j] : a[j + 2], 16, 64);
+  double c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8, 64);
+  c += __shfl_xor(c, 4, 64);
+  c += __shfl_xor(c, 2, 64);
+  c += __shfl_xor(c, 1, 64);
+  return c;
+}
+
 // y(0:m) = alpha X(0:m, 0:k) x + beta y   (x with stride incx; y distinct
 // from X and x)
-__device__ void wg_gemv_n(int m, int k, double alpha, const double* X, int ldx, const double* x,
-                          int incx, double beta, double* y) {
+__device__ __noinline__ void wg_gemv_n(int m, int k, double alpha, const double* X, int ldx, const double* x,
+                          int incx, double beta, double* y, Lds& ls) {
+  stage_vec(ls.xs, x, k, incx);
   for (int i = threadIdx.x; i < m; i += kBT) {
-    double s = 0.0;
-    for (int c = 0; c < k; ++c) s = fma(X[i + (size_t)c * ldx], x[(size_t)c * incx], s);
+    const double s = row_dot(X + i, ldx, ls.xs, 0, k);
     y[i] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[i]);
   }
   __syncthreads();
 }
 
-// z(0:k) = alpha X(0:m, 0:k)^T x + beta z: one wavefront per column
-__device__ void wg_gemv_t(int m, int k, double alpha, const double* X, int ldx, const double* x,
-                          double beta, double* z) {
+// z(0:k) = alpha X(0:m, 0:k)^T x + beta z: each wavefront takes eight
+// columns at a time (lanes split the rows, two rows per lane in flight) and
+// reduces them together with wave_sum8.  upper: X is upper triangular with
+// zeros below the diagonal, so column c needs rows 0..c only.
+__device__ __noinline__ void wg_gemv_t_core(int m, int k, double alpha, const double* X, int ldx,
+                                            double beta, double* z, bool upper, Lds& ls) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int c = wv; c < k; c += kBNW) {
-    double s = 0.0;
-    for (int i = lane; i < m; i += 64) s = fma(X[i + (size_t)c * ldx], x[i], s);
-    s = wave_sum(s);
-    if (lane == 0) z[c] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * z[c]);
+  for (int c0 = 8 * wv; c0 < k; c0 += 8 * kBNW) {
+    const int nc = min(8, k - c0);
+    const int mr = upper ? min(m, c0 + 8) : m;
+    // columns past the last one repeat it; their sums are not stored
+    const double* colq[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) colq[q] = X + (size_t)(c0 + min(q, nc - 1)) * ldx;
+    double v[8], u[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = u[q] = 0.0;
+    int i = lane;
+    for (; i + 64 < mr; i += 128) {
+      const double x0 = ls.xs[i], x1 = ls.xs[i + 64];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        v[q] = fma(colq[q][i], x0, v[q]);
+        u[q] = fma(colq[q][i + 64], x1, u[q]);
+      }
+    }
+    if (i < mr) {
+      const double x0 = ls.xs[i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = fma(colq[q][i], x0, v[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] += u[q];
+    const double s = wave_sum8(v);
+    const int c = c0 + ((lane >> 3) & 7);
+    if ((lane & 7) == 0 && c < k) z[c] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * z[c]);
   }
   __syncthreads();
 }
 
+__device__ void wg_gemv_t(int m, int k, double alpha, const double* X, int ldx, const double* x,
+                          double beta, double* z, Lds& ls) {
+  stage_vec(ls.xs, x, m, 1);
+  wg_gemv_t_core(m, k, alpha, X, ldx, beta, z, false, ls);
+}
+
+// Upper triangular products of the workgroup.  The strictly lower triangles
+// of B (zeroed on entry and kept zero), S and T (zeroed at each panel start)
+// are exact zeros, so every wavefront starts its rows at the column of its
+// first row: all lanes then read the same columns (coalesced), and the few
+// zeros below the diagonal add nothing.
+
 // y = alpha op(T) x for upper triangular T (k x k); y distinct from x
 __device__ void wg_trmv_small(bool trans, int k, const double* T, int ldt, const double* x,
-                              double alpha, double* y) {
-  for (int t = threadIdx.x; t < k; t += kBT) {
-    double s = 0.0;
-    if (!trans) {
-      for (int c = t; c < k; ++c) s = fma(T[t + (size_t)c * ldt], x[c], s);
-    } else {
-      for (int c = 0; c <= t; ++c) s = fma(T[c + (size_t)t * ldt], x[c], s);
-    }
-    y[t] = alpha * s;
+                              double alpha, double* y, Lds& ls) {
+  stage_vec(ls.xs, x, k, 1);
+  if (trans) {
+    wg_gemv_t_core(k, k, alpha, T, ldt, 0.0, y, true, ls);
+    return;
   }
+  const int lane = threadIdx.x & 63;
+  for (int t = threadIdx.x; t < k; t += kBT) y[t] = alpha * row_dot(T + t, ldt, ls.xs, t - lane, k);
   __syncthreads();
 }
 
 // Compact-WY append (Sec. 2.4): T(0:kk, kk) = -tau T(0:kk, 0:kk) z, T(kk, kk) = tau
-__device__ void wg_wy_append(double* T, int ldt, int kk, const double* z, double tau) {
-  for (int t = threadIdx.x; t < kk; t += kBT) {
-    double s = 0.0;
-    for (int c = t; c < kk; ++c) s = fma(T[t + (size_t)c * ldt], z[c], s);
-    T[t + (size_t)kk * ldt] = -tau * s;
-  }
+__device__ __noinline__ void wg_wy_append(double* T, int ldt, int kk, const double* z, double tau, Lds& ls) {
+  stage_vec(ls.xs, z, kk, 1);
+  const int lane = threadIdx.x & 63;
+  for (int t = threadIdx.x; t < kk; t += kBT)
+    T[t + (size_t)kk * ldt] = -tau * row_dot(T + t, ldt, ls.xs, t - lane, kk);
   if (threadIdx.x == 0) T[kk + (size_t)kk * ldt] = tau;
   __syncthreads();
 }
 
 // Householder reflector of x (length m), LAPACK convention: v[0] = 1,
 // (I - tau v v^T) x = beta e1; x overwritten with (beta, 0, ...) if asked.
-__device__ void wg_house(int m, double* x, double* v, double& tau, double& beta, bool overwrite,
+__device__ __noinline__ void wg_house(int m, double* x, double* v, double& tau, double& beta, bool overwrite,
                          double* sh) {
   const double alpha = x[0];
   double amax = 0.0;
@@ -187,40 +282,68 @@ __device__ void wg_house(int m, double* x, double* v, double& tau, double& beta,
   __syncthreads();
 }
 
-// C(0:m, 0:n) = alpha op(A) op(B) + beta C   (plain loops; C distinct from A, B)
-//   op(A): m x k (A or A^T),  op(B): k x n (B or B^T)
-__device__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
-                        int lda, const double* B, int ldb, double beta, double* C, int ldc) {
-  for (int c = 0; c < n; ++c) {
-    for (int i = threadIdx.x; i < m; i += kBT) {
-      double s = 0.0;
-      for (int l = 0; l < k; ++l) {
-        const double a = ta ? A[l + (size_t)i * lda] : A[i + (size_t)l * lda];
-        const double b = tb ? B[c + (size_t)l * ldb] : B[l + (size_t)c * ldb];
-        s = fma(a, b, s);
-      }
-      double* p = C + i + (size_t)c * ldc;
-      *p = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *p);
+// C(0:m, 0:n) = alpha op(A) op(B) + beta C (C distinct from A, B).
+//   op(A): m x k (A or A^T),  op(B): k x n (B or B^T); k <= kBMax.
+// Eight columns of op(B) at a time are staged in LDS; each thread forms
+// eight outputs of a row with every A entry it loads, four loads in flight.
+__device__ __noinline__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
+                        int lda, const double* B, int ldb, double beta, double* C, int ldc,
+                        Lds& ls) {
+  constexpr int NC = 8;
+  for (int c0 = 0; c0 < n; c0 += NC) {
+    const int nc = min(NC, n - c0);
+    for (int idx = threadIdx.x; idx < NC * k; idx += kBT) {
+      const int l = idx % k, cc = idx / k;
+      ls.bs[idx] = (cc < nc) ? (tb ? B[(c0 + cc) + (size_t)l * ldb] : B[l + (size_t)(c0 + cc) * ldb])
+                            : 0.0;
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += kBT) {
+      double sv[NC];
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) sv[cc] = 0.0;
+      const double* a = ta ? A + (size_t)i * lda : A + i;
+      const size_t as = ta ? 1 : (size_t)lda;
+      int l = 0;
+      for (; l + 4 <= k; l += 4) {
+        double av[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) av[u] = a[(size_t)(l + u) * as];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int cc = 0; cc < NC; ++cc) sv[cc] = fma(av[u], ls.bs[cc * k + l + u], sv[cc]);
+      }
+      for (; l < k; ++l) {
+        const double av = a[(size_t)l * as];
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) sv[cc] = fma(av, ls.bs[cc * k + l], sv[cc]);
+      }
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc)
+        if (cc < nc) {
+          double* p = C + i + (size_t)(c0 + cc) * ldc;
+          *p = (beta == 0.0) ? alpha * sv[cc] : fma(alpha, sv[cc], beta * *p);
+        }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// y = B(0:m, 0:m) x for upper triangular B; y distinct from x
-__device__ void wg_trmv_upper(int m, const double* B, int ldb, const double* x, double* y) {
-  for (int i = threadIdx.x; i < m; i += kBT) {
-    double s = 0.0;
-    for (int c = i; c < m; ++c) s = fma(B[i + (size_t)c * ldb], x[c], s);
-    y[i] = s;
-  }
+// y = B(0:m, 0:m) x for upper triangular B (zeros below the diagonal, read
+// as in wg_trmv_small); y distinct from x
+__device__ __noinline__ void wg_trmv_upper(int m, const double* B, int ldb, const double* x, double* y, Lds& ls) {
+  stage_vec(ls.xs, x, m, 1);
+  const int lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < m; i += kBT) y[i] = row_dot(B + i, ldb, ls.xs, i - lane, m);
   __syncthreads();
 }
 
 // Scaled back substitution: B(0:m, 0:m) x = 2^{-E} c, returns E >= 0.
 // r (LDS, m doubles) carries the right-hand side and then x; dg (LDS) holds
-// one 64 x 64 diagonal tile.  Wavefront 0 substitutes a 64-row block; any
+// one 64 x 64 diagonal tile (leading dimension kTileLd).  Wavefront 0 substitutes a 64-row block; any
 // rescaling it needs is then applied to all other entries by everyone.
-__device__ int wg_trsv(int m, const double* B, int ldb, const double* c, double* x, double* r,
+__device__ __noinline__ int wg_trsv(int m, const double* B, int ldb, const double* c, double* x, double* r,
                        double* dg, int* shi) {
   for (int i = threadIdx.x; i < m; i += kBT) r[i] = c[i];
   int E = 0;
@@ -228,16 +351,26 @@ __device__ int wg_trsv(int m, const double* B, int ldb, const double* c, double*
   __syncthreads();
   for (int b = (m + 63) / 64 - 1; b >= 0; --b) {
     const int r0 = 64 * b, nr = min(64, m - r0);
-    for (int idx = threadIdx.x; idx < 64 * 64; idx += kBT) {
-      const int rr = idx & 63, cc = idx >> 6;
-      dg[rr + cc * 65] =
-          (rr < nr && cc < nr && rr <= cc) ? B[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ldb] : 0.0;
+    {
+      // all sixteen loads of a thread are issued before the LDS stores
+      double t[64 * 64 / kBT];
+#pragma unroll
+      for (int q = 0; q < 64 * 64 / kBT; ++q) {
+        const int idx = threadIdx.x + q * kBT, rr = idx & 63, cc = idx >> 6;
+        t[q] = (rr < nr && cc < nr && rr <= cc) ? B[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ldb]
+                                                 : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 64 * 64 / kBT; ++q) {
+        const int idx = threadIdx.x + q * kBT;
+        dg[(idx & 63) + (idx >> 6) * kTileLd] = t[q];
+      }
     }
     __syncthreads();
     if (wv == 0) {
       const bool live = lane < nr;
       double rhs = live ? r[r0 + lane] : 0.0;
-      const double d_own = live ? dg[lane * 65 + lane] : 1.0;
+      const double d_own = live ? dg[lane * kTileLd + lane] : 1.0;
       const double dp = (d_own != 0.0) ? d_own : 1.0;  // zero pivots only when B = 0
       const double dinv = 1.0 / dp;
       int shr = 0;
@@ -253,7 +386,7 @@ __device__ int wg_trsv(int m, const double* B, int ldb, const double* c, double*
         }
         const double xr = t * readlane_d(dinv, rr);
         if (lane == rr) rhs = xr;
-        if (lane < rr) rhs = fma(-dg[rr * 65 + lane], xr, rhs);
+        if (lane < rr) rhs = fma(-dg[rr * kTileLd + lane], xr, rhs);
       }
       if (live) r[r0 + lane] = rhs;
       if (lane == 0) shi[0] = shr;
@@ -266,9 +399,8 @@ __device__ int wg_trsv(int m, const double* B, int ldb, const double* c, double*
     for (int i = r0 + 64 + threadIdx.x; i < m; i += kBT)
       if (shr) r[i] = ldexp(r[i], -kShrinkExp * shr);
     for (int i = threadIdx.x; i < r0; i += kBT) {
-      double acc = shr ? ldexp(r[i], -kShrinkExp * shr) : r[i];
-      for (int cc = 0; cc < nr; ++cc) acc = fma(-B[(size_t)i + (size_t)(r0 + cc) * ldb], r[r0 + cc], acc);
-      r[i] = acc;
+      const double acc = shr ? ldexp(r[i], -kShrinkExp * shr) : r[i];
+      r[i] = acc - row_dot(B + i + (size_t)r0 * ldb, ldb, r + r0, 0, nr);
     }
     __syncthreads();
   }
@@ -279,20 +411,20 @@ __device__ int wg_trsv(int m, const double* B, int ldb, const double* c, double*
 
 // X(rows, cols) -= (X V) T V^T on the column range of the panel's local
 // frame: X is rows x L (leading dimension ldx), V L x k, T k x k.
-__device__ void wg_right_wy(int rows, int L, int k, double* X, int ldx, const double* V,
-                            const double* T, const BWork& w) {
+__device__ __noinline__ void wg_right_wy(int rows, int L, int k, double* X, int ldx, const double* V,
+                            const double* T, const BWork& w, Lds& ls) {
   if (rows <= 0 || k <= 0) return;
-  wg_gemm(false, false, rows, k, L, 1.0, X, ldx, V, w.ld, 0.0, w.P, w.ld);
-  wg_gemm(false, false, rows, k, k, 1.0, w.P, w.ld, T, w.ld, 0.0, w.P2, w.ld);
-  wg_gemm(false, true, rows, L, k, -1.0, w.P2, w.ld, V, w.ld, 1.0, X, ldx);
+  wg_gemm(false, false, rows, k, L, 1.0, X, ldx, V, w.ld, 0.0, w.P, w.ld, ls);
+  wg_gemm(false, false, rows, k, k, 1.0, w.P, w.ld, T, w.ld, 0.0, w.P2, w.ld, ls);
+  wg_gemm(false, true, rows, L, k, -1.0, w.P2, w.ld, V, w.ld, 1.0, X, ldx, ls);
 }
 // X(0:L, cols) -= U S^T (U^T X): X is L x ncols
-__device__ void wg_left_wy(int L, int ncols, int k, double* X, int ldx, const double* U,
-                           const double* S, const BWork& w) {
+__device__ __noinline__ void wg_left_wy(int L, int ncols, int k, double* X, int ldx, const double* U,
+                           const double* S, const BWork& w, Lds& ls) {
   if (ncols <= 0 || k <= 0) return;
-  wg_gemm(true, false, k, ncols, L, 1.0, U, w.ld, X, ldx, 0.0, w.P, w.ld);
-  wg_gemm(true, false, k, ncols, k, 1.0, S, w.ld, w.P, w.ld, 0.0, w.P2, w.ld);
-  wg_gemm(false, false, L, ncols, k, -1.0, U, w.ld, w.P2, w.ld, 1.0, X, ldx);
+  wg_gemm(true, false, k, ncols, L, 1.0, U, w.ld, X, ldx, 0.0, w.P, w.ld, ls);
+  wg_gemm(true, false, k, ncols, k, 1.0, S, w.ld, w.P, w.ld, 0.0, w.P2, w.ld, ls);
+  wg_gemm(false, false, L, ncols, k, -1.0, U, w.ld, w.P2, w.ld, 1.0, X, ldx, ls);
 }
 
 struct Pencil {
@@ -302,18 +434,18 @@ struct Pencil {
 
 // Factored solve (Sec. 3.2.2 c): ctil <- (I - U S U^T) ctil (nu reflectors),
 // B(s+1:n, s+1:n) ysol = 2^{-E} ctil, ysol <- (I - V T^T V^T) ysol (kk).
-__device__ int factored_solve(const Pencil& P, const BWork& w, int s, int kk, int nu, double* ctil,
-                              double* ysol, double* r, double* dg, int* shi) {
+__device__ __noinline__ int factored_solve(const Pencil& P, const BWork& w, int s, int kk, int nu, double* ctil,
+                              double* ysol, double* r, double* dg, int* shi, Lds& ls) {
   const int L = P.n - s - 1;
-  wg_gemv_t(L, nu, 1.0, w.U, w.ld, ctil, 0.0, w.tk);
-  wg_trmv_small(false, nu, w.S, w.ld, w.tk, 1.0, w.tk2);
-  wg_gemv_n(L, nu, -1.0, w.U, w.ld, w.tk2, 1, 1.0, ctil);
+  wg_gemv_t(L, nu, 1.0, w.U, w.ld, ctil, 0.0, w.tk, ls);
+  wg_trmv_small(false, nu, w.S, w.ld, w.tk, 1.0, w.tk2, ls);
+  wg_gemv_n(L, nu, -1.0, w.U, w.ld, w.tk2, 1, 1.0, ctil, ls);
   const double* Bp = P.B + (size_t)(s + 1) + (size_t)(s + 1) * P.ld;
   const int E = wg_trsv(L, Bp, P.ld, ctil, ysol, r, dg, shi);
   if (kk > 0) {
-    wg_gemv_t(L, kk, 1.0, w.V, w.ld, ysol, 0.0, w.tk);
-    wg_trmv_small(true, kk, w.T, w.ld, w.tk, 1.0, w.tk2);
-    wg_gemv_n(L, kk, -1.0, w.V, w.ld, w.tk2, 1, 1.0, ysol);
+    wg_gemv_t(L, kk, 1.0, w.V, w.ld, ysol, 0.0, w.tk, ls);
+    wg_trmv_small(true, kk, w.T, w.ld, w.tk, 1.0, w.tk2, ls);
+    wg_gemv_n(L, kk, -1.0, w.V, w.ld, w.tk2, 1, 1.0, ysol, ls);
   }
   return E;
 }
@@ -321,19 +453,19 @@ __device__ int factored_solve(const Pencil& P, const BWork& w, int s, int kk, in
 // Residual of the refined solve (Sec. 3.2.2 c): w = (I - V T V^T)[0; x],
 // w = B w, w = (I - U S^T U^T) w, r = 2^{-E} e1 - w(kk:); returns whether
 // ||r|| <= tol_factor u ||B||_F ||x||.
-__device__ bool residual(const Pencil& P, const BWork& w, int s, int kk, const double* x, int E,
-                         double normB, double tol_factor, double* sh) {
+__device__ __noinline__ bool residual(const Pencil& P, const BWork& w, int s, int kk, const double* x, int E,
+                         double normB, double tol_factor, double* sh, Lds& ls) {
   const int L = P.n - s - 1, m = L - kk;
   for (int i = threadIdx.x; i < L; i += kBT) w.wv[i] = (i < kk) ? 0.0 : x[i - kk];
   __syncthreads();
-  wg_gemv_t(m, kk, 1.0, w.V + kk, w.ld, x, 0.0, w.tk);
-  wg_trmv_small(false, kk, w.T, w.ld, w.tk, 1.0, w.tk2);
-  wg_gemv_n(L, kk, -1.0, w.V, w.ld, w.tk2, 1, 1.0, w.wv);
+  wg_gemv_t(m, kk, 1.0, w.V + kk, w.ld, x, 0.0, w.tk, ls);
+  wg_trmv_small(false, kk, w.T, w.ld, w.tk, 1.0, w.tk2, ls);
+  wg_gemv_n(L, kk, -1.0, w.V, w.ld, w.tk2, 1, 1.0, w.wv, ls);
   const double* Bp = P.B + (size_t)(s + 1) + (size_t)(s + 1) * P.ld;
-  wg_trmv_upper(L, Bp, P.ld, w.wv, w.w2);
-  wg_gemv_t(L, kk + 1, 1.0, w.U, w.ld, w.w2, 0.0, w.tk);
-  wg_trmv_small(true, kk + 1, w.S, w.ld, w.tk, 1.0, w.tk2);
-  wg_gemv_n(L, kk + 1, -1.0, w.U, w.ld, w.tk2, 1, 1.0, w.w2);
+  wg_trmv_upper(L, Bp, P.ld, w.wv, w.w2, ls);
+  wg_gemv_t(L, kk + 1, 1.0, w.U, w.ld, w.w2, 0.0, w.tk, ls);
+  wg_trmv_small(true, kk + 1, w.S, w.ld, w.tk, 1.0, w.tk2, ls);
+  wg_gemv_n(L, kk + 1, -1.0, w.U, w.ld, w.tk2, 1, 1.0, w.w2, ls);
   double rmax = 0.0, xmax = 0.0;
   for (int i = threadIdx.x; i < m; i += kBT) {
     const double ri = ldexp(i == 0 ? 1.0 : 0.0, -E) - w.w2[kk + i];
@@ -358,7 +490,7 @@ __device__ bool residual(const Pencil& P, const BWork& w, int s, int kk, const d
 
 // Householder QR of B(c0:n, c0:n) (restores a triangular trailing block);
 // each reflector is applied to B(c:n, c+1:n), A(c:n, a0:n) and Q(:, c:n).
-__device__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0, double* sh) {
+__device__ __noinline__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0, double* sh, Lds& ls) {
   const int n = P.n, ld = P.ld;
   for (int c = c0; c < n - 1; ++c) {
     const int m = n - c;
@@ -393,28 +525,28 @@ __device__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0,
 // Absorb the k reflector pairs of the panel starting at column s; columns
 // s..j-1 (j = s+k) are reduced, columns j..n-1 still carry the pending
 // updates.  failed: the panel ended at column j by a refinement failure.
-__device__ void absorb_dense(const Pencil& P, const BWork& w, int s, int k, bool failed,
-                             double* sh) {
+__device__ __noinline__ void absorb_dense(const Pencil& P, const BWork& w, int s, int k, bool failed,
+                             double* sh, Lds& ls) {
   const int n = P.n, ld = P.ld, L = n - s - 1, j = s + k;
   if (k > 0) {
     // A: rows 0..s take the right transformation on columns s+1..n-1; rows
     // s+1.. of the unreduced columns j..n-1 take the column update (a)
-    wg_right_wy(s + 1, L, k, P.A + (size_t)(s + 1) * ld, ld, w.V, w.T, w);
+    wg_right_wy(s + 1, L, k, P.A + (size_t)(s + 1) * ld, ld, w.V, w.T, w, ls);
     double* Aj = P.A + (size_t)(s + 1) + (size_t)j * ld;
-    wg_gemm(false, true, L, n - j, k, -1.0, w.Y, w.ld, w.V + (j - s - 1), w.ld, 1.0, Aj, ld);
-    wg_left_wy(L, n - j, k, Aj, ld, w.U, w.S, w);
+    wg_gemm(false, true, L, n - j, k, -1.0, w.Y, w.ld, w.V + (j - s - 1), w.ld, 1.0, Aj, ld, ls);
+    wg_left_wy(L, n - j, k, Aj, ld, w.U, w.S, w, ls);
     // B: (I - U S^T U^T) B (I - V T V^T) on rows/columns s+1..n-1 (rows
     // 0..s only from the right)
-    wg_right_wy(n, L, k, P.B + (size_t)(s + 1) * ld, ld, w.V, w.T, w);
-    wg_left_wy(L, L, k, P.B + (size_t)(s + 1) + (size_t)(s + 1) * ld, ld, w.U, w.S, w);
+    wg_right_wy(n, L, k, P.B + (size_t)(s + 1) * ld, ld, w.V, w.T, w, ls);
+    wg_left_wy(L, L, k, P.B + (size_t)(s + 1) + (size_t)(s + 1) * ld, ld, w.U, w.S, w, ls);
     // Q <- Q (I - U S U^T), Z <- Z (I - V T V^T) on columns s+1..n-1
     {
       double* X = P.Q + (size_t)(s + 1) * ld;
-      wg_gemm(false, false, n, k, L, 1.0, X, ld, w.U, w.ld, 0.0, w.P, w.ld);
-      wg_gemm(false, false, n, k, k, 1.0, w.P, w.ld, w.S, w.ld, 0.0, w.P2, w.ld);
-      wg_gemm(false, true, n, L, k, -1.0, w.P2, w.ld, w.U, w.ld, 1.0, X, ld);
+      wg_gemm(false, false, n, k, L, 1.0, X, ld, w.U, w.ld, 0.0, w.P, w.ld, ls);
+      wg_gemm(false, false, n, k, k, 1.0, w.P, w.ld, w.S, w.ld, 0.0, w.P2, w.ld, ls);
+      wg_gemm(false, true, n, L, k, -1.0, w.P2, w.ld, w.U, w.ld, 1.0, X, ld, ls);
     }
-    wg_right_wy(n, L, k, P.Z + (size_t)(s + 1) * ld, ld, w.V, w.T, w);
+    wg_right_wy(n, L, k, P.Z + (size_t)(s + 1) * ld, ld, w.V, w.T, w, ls);
   }
   // reduced columns of B: the entries below the diagonal are rounding noise
   // of the opposite reflectors (Lemma 2.1)
@@ -422,11 +554,19 @@ __device__ void absorb_dense(const Pencil& P, const BWork& w, int s, int k, bool
   for (int c = s + 1; c <= clast && c < n; ++c)
     for (int i = c + 1 + threadIdx.x; i < n; i += kBT) P.B[i + (size_t)c * ld] = 0.0;
   __syncthreads();
-  if (failed) retriangularise(P, w, j + 1, j, sh);
+  if (failed) retriangularise(P, w, j + 1, j, sh, ls);
 }
 
-__device__ void reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& w, uint64_t seed,
-                              double* r, double* dg, int* shi, double* sh) {
+// Counters of one pencil's reduction: panels (absorptions), refinement
+// steps, and device-clock ticks spent in the solves, the residuals and the
+// absorptions (read by thread 0 between the helpers' closing barriers).
+struct PencilCount {
+  int panels, ir;
+  int64_t t_solve, t_resid, t_absorb;
+};
+
+__device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& w, uint64_t seed,
+                              double* r, double* dg, int* shi, double* sh, Lds& ls) {
   const int n = P.n, ld = P.ld;
   // Q = Z = I; B's strict lower triangle ignored on entry
   for (int c = 0; c < n; ++c)
@@ -450,7 +590,14 @@ __device__ void reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& 
     }
   bss = block_sum(bss, sh);
   const double normB = sqrt(bss) / bsc;
-  if (n <= 2) return;
+  PencilCount cnt = {0, 0, 0, 0, 0};
+  if (n <= 2) return cnt;
+  int64_t tc = 0;
+  auto tick = [&](int64_t& acc) {
+    const int64_t now = (int64_t)wall_clock64();
+    acc += now - tc;
+    tc = now;
+  };
 
   int s = 0;
   uint64_t panel = 0;
@@ -480,35 +627,43 @@ __device__ void reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& 
       wg_copy(w.acol, acol, L);
       // (a) column update with the kk pending pairs
       if (kk > 0) {
-        wg_gemv_n(L, kk, -1.0, w.Y, w.ld, w.V + (kk - 1), w.ld, 1.0, acol);
-        wg_gemv_t(L, kk, 1.0, w.U, w.ld, acol, 0.0, w.tk);
-        wg_trmv_small(true, kk, w.S, w.ld, w.tk, 1.0, w.tk2);
-        wg_gemv_n(L, kk, -1.0, w.U, w.ld, w.tk2, 1, 1.0, acol);
+        wg_gemv_n(L, kk, -1.0, w.Y, w.ld, w.V + (kk - 1), w.ld, 1.0, acol, ls);
+        wg_gemv_t(L, kk, 1.0, w.U, w.ld, acol, 0.0, w.tk, ls);
+        wg_trmv_small(true, kk, w.S, w.ld, w.tk, 1.0, w.tk2, ls);
+        wg_gemv_n(L, kk, -1.0, w.U, w.ld, w.tk2, 1, 1.0, acol, ls);
       }
       // (b) left reflector, S
       const int m = L - kk;
       double* ucol = w.U + kk + (size_t)kk * w.ld;
       double tau_u, beta_u;
       wg_house(m, acol + kk, ucol, tau_u, beta_u, true, sh);
-      if (kk > 0) wg_gemv_t(m, kk, 1.0, w.U + kk, w.ld, ucol, 0.0, w.tk);
-      wg_wy_append(w.S, w.ld, kk, w.tk, tau_u);
+      if (kk > 0) wg_gemv_t(m, kk, 1.0, w.U + kk, w.ld, ucol, 0.0, w.tk, ls);
+      wg_wy_append(w.S, w.ld, kk, w.tk, tau_u, ls);
       // (c) solve, with refinement from the second column on
       wg_fill(w.ctil, L, 0.0);
       if (threadIdx.x == 0) w.ctil[kk] = 1.0;
       __syncthreads();
-      int E = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.ysol, r, dg, shi);
+      tc = (int64_t)wall_clock64();
+      int E = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.ysol, r, dg, shi, ls);
+      tick(cnt.t_solve);
       double* x = w.ysol + kk;
       bool ok = true;
       if (kk > 0) {
-        bool st = residual(P, w, s, kk, x, E, normB, a.tol_factor, sh);
+        bool st = residual(P, w, s, kk, x, E, normB, a.tol_factor, sh, ls);
+        tick(cnt.t_resid);
         for (int it = 0; !st && it < a.max_ir; ++it) {
           for (int i = threadIdx.x; i < L; i += kBT) w.ctil[i] = (i < kk) ? 0.0 : w.rv[i - kk];
           __syncthreads();
-          const int E2 = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.dsol, r, dg, shi);
+          tc = (int64_t)wall_clock64();
+          const int E2 = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.dsol, r, dg, shi, ls);
+          tick(cnt.t_solve);
           for (int i = threadIdx.x; i < m; i += kBT) x[i] = ldexp(x[i], -E2) + w.dsol[kk + i];
           __syncthreads();
           E += E2;
-          st = residual(P, w, s, kk, x, E, normB, a.tol_factor, sh);
+          tc = (int64_t)wall_clock64();
+          st = residual(P, w, s, kk, x, E, normB, a.tol_factor, sh, ls);
+          tick(cnt.t_resid);
+          ++cnt.ir;
         }
         ok = st;
       }
@@ -521,19 +676,23 @@ __device__ void reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& 
       double* vcol = w.V + kk + (size_t)kk * w.ld;
       double tau_v, beta_v;
       wg_house(m, x, vcol, tau_v, beta_v, false, sh);
-      if (kk > 0) wg_gemv_t(m, kk, 1.0, w.V + kk, w.ld, vcol, 0.0, w.tk);
-      wg_wy_append(w.T, w.ld, kk, w.tk, tau_v);
+      if (kk > 0) wg_gemv_t(m, kk, 1.0, w.V + kk, w.ld, vcol, 0.0, w.tk, ls);
+      wg_wy_append(w.T, w.ld, kk, w.tk, tau_v, ls);
       double* ycol = w.Y + (size_t)kk * w.ld;
-      wg_gemv_n(L, m, 1.0, P.A + (size_t)(s + 1) + (size_t)(j + 1) * ld, ld, vcol, 1, 0.0, ycol);
-      if (kk > 0) wg_gemv_n(L, kk, -1.0, w.Y, w.ld, w.tk, 1, 1.0, ycol);
+      wg_gemv_n(L, m, 1.0, P.A + (size_t)(s + 1) + (size_t)(j + 1) * ld, ld, vcol, 1, 0.0, ycol, ls);
+      if (kk > 0) wg_gemv_n(L, kk, -1.0, w.Y, w.ld, w.tk, 1, 1.0, ycol, ls);
       for (int i = threadIdx.x; i < L; i += kBT) ycol[i] *= tau_v;
       __syncthreads();
       k = kk + 1;
     }
-    absorb_dense(P, w, s, k, failed, sh);
+    tc = (int64_t)wall_clock64();
+    absorb_dense(P, w, s, k, failed, sh, ls);
+    tick(cnt.t_absorb);
     s += k;
     ++panel;
   }
+  cnt.panels = (int)panel;
+  return cnt;
 }
 
 // Counting sort of the pencils by decreasing order; resets the ticket.
@@ -560,11 +719,14 @@ __global__ __launch_bounds__(1024) void k_batched_order(BatchArgs a) {
   if (threadIdx.x == 0) a.counter[0] = 0;
 }
 
-__global__ __launch_bounds__(kBT) void k_batched(BatchArgs a) {
+// Two workgroups per CU: the helpers above are kept out of line so that
+// each is register-allocated on its own (no spills inside their loops).
+__global__ __launch_bounds__(kBT, 2) void k_batched(BatchArgs a) {
   __shared__ double r[kBMax];
-  __shared__ double dg[64 * 65];
   __shared__ double sh[kBNW];
   __shared__ int shi[2];
+  __shared__ Lds ls;
+  double* dg = ls.bs;  // the solve's diagonal tile shares the operand block
   const BWork w = bwork(a.scratch + (size_t)blockIdx.x * a.scratch_stride, a.nmax);
   for (;;) {
     if (threadIdx.x == 0) shi[1] = atomicAdd(a.counter, 1);
@@ -580,13 +742,27 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchArgs a) {
     P.B = a.B[pi];
     P.Q = a.Q[pi];
     P.Z = a.Z[pi];
+    const int64_t t0 = (int64_t)wall_clock64();
     int info = 0;
+    PencilCount cnt = {0, 0, 0, 0, 0};
     if (P.n < 0 || P.n > a.nmax || P.ld < max(1, P.n) ||
         (P.n > 0 && (!P.A || !P.B || !P.Q || !P.Z)))
       info = -1;
     else
-      reduce_pencil(a, P, w, a.seed ^ splitmix64((uint64_t)pi + 1), r, dg, shi, sh);
-    if (threadIdx.x == 0) a.info[pi] = info;
+      cnt = reduce_pencil(a, P, w, a.seed ^ splitmix64((uint64_t)pi + 1), r, dg, shi, sh, ls);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.info[pi] = info;
+      int64_t* st = a.stats + kStatWords * (size_t)pi;
+      st[0] = t0;
+      st[1] = (int64_t)wall_clock64();
+      st[2] = cnt.panels;
+      st[3] = cnt.ir;
+      st[4] = cnt.t_solve;
+      st[5] = cnt.t_resid;
+      st[6] = cnt.t_absorb;
+      st[7] = 0;
+    }
     __syncthreads();
   }
 }
@@ -597,11 +773,18 @@ size_t batch_stride(int nmax) {
   return (d * 8 + 255) / 256 * 32;  // doubles, rounded to 256 bytes
 }
 
+size_t order_bytes(int batch) { return ((size_t)batch * 4 + 255) / 256 * 256; }
+size_t stats_bytes(int batch) { return ((size_t)batch * kStatWords * 8 + 255) / 256 * 256; }
+
 }  // namespace
 
 size_t batched_workspace_bytes(int batch, int nmax) {
   if (batch <= 0) return 256;
-  return 256 + ((size_t)batch * 4 + 255) / 256 * 256 + batch_grid(batch) * batch_stride(nmax) * 8;
+  return 256 + order_bytes(batch) + stats_bytes(batch) + batch_grid(batch) * batch_stride(nmax) * 8;
+}
+
+const int64_t* batched_stats_ptr(const void* workspace, int batch) {
+  return (const int64_t*)((const char*)workspace + 256 + order_bytes(batch));
 }
 
 int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* const* A_dev,
@@ -623,7 +806,8 @@ int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* cons
   a.info = info_dev;
   a.counter = (int*)base;
   a.order = (int*)(base + 256);
-  a.scratch = (double*)(base + 256 + ((size_t)batch * 4 + 255) / 256 * 256);
+  a.stats = (int64_t*)(base + 256 + order_bytes(batch));
+  a.scratch = (double*)(base + 256 + order_bytes(batch) + stats_bytes(batch));
   a.scratch_stride = batch_stride(a.nmax);
   a.tol_factor = tol_factor;
   a.seed = seed;

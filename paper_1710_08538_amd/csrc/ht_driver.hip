@@ -854,4 +854,39 @@ int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
   return HT_OK;
 }
 
+int ht_batched_pencil_stats(const void* workspace, int32_t batch, int64_t* out, void* stream) {
+  constexpr int W = 8;  // words per pencil in the device record
+  if (batch < 0) return -2;
+  if (batch == 0) return HT_OK;
+  if (!workspace) return -1;
+  if (!out) return -3;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int64_t> raw((size_t)batch * W);
+  if (hipMemcpyAsync(raw.data(), batched_stats_ptr(workspace, batch), raw.size() * 8,
+                     hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return HT_ERR_HIP;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    return HT_ERR_HIP;
+  int64_t t0 = raw[0];
+  for (int i = 1; i < batch; ++i) t0 = std::min(t0, raw[W * (size_t)i]);
+  const double ns_per_tick = 1.0e6 / (double)khz;
+  auto ns = [&](int64_t ticks) { return (int64_t)((double)ticks * ns_per_tick); };
+  for (int i = 0; i < batch; ++i) {
+    const int64_t* r = &raw[W * (size_t)i];
+    int64_t* o = out + 8 * (size_t)i;
+    o[0] = ns(r[0] - t0);
+    o[1] = ns(r[1] - t0);
+    o[2] = r[2];
+    o[3] = r[3];
+    o[4] = ns(r[4]);
+    o[5] = ns(r[5]);
+    o[6] = ns(r[6]);
+    o[7] = 0;
+  }
+  return HT_OK;
+}
+
 }  // extern "C"

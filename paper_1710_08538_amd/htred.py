@@ -76,6 +76,8 @@ def lib():
                                         ctypes.c_int32, ctypes.POINTER(Options), vp,
                                         ctypes.c_size_t, vp]
         L.ht_reduce_batched.restype = ctypes.c_int
+        L.ht_batched_pencil_stats.argtypes = [vp, ctypes.c_int32, vp, vp]
+        L.ht_batched_pencil_stats.restype = ctypes.c_int
         L.ht_strerror.argtypes = [ctypes.c_int]
         L.ht_strerror.restype = ctypes.c_char_p
         L.ht_version.argtypes = []
@@ -201,6 +203,16 @@ class BatchedPlan:
                                      ctypes.byref(self.opt), self.ws.data_ptr(),
                                      self.ws.numel(), s.cuda_stream)
         _check(rc)
+
+    def pencil_stats(self, stream=None):
+        """Per-pencil record of the last run as a host int64 tensor of shape
+        (batch, 8): start_ns, end_ns, panels, ir_steps, solve_ns, residual_ns,
+        absorb_ns, 0.  Waits for the stream."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        out = torch.zeros((max(self.batch, 1), 8), dtype=torch.int64)
+        _check(lib().ht_batched_pencil_stats(self.ws.data_ptr(), self.batch, out.data_ptr(),
+                                             s.cuda_stream))
+        return out[:self.batch]
 
 
 def reduce_batched(As, Bs, Qs=None, Zs=None, **kw):

@@ -48,6 +48,37 @@ def test_batched_parity_mixed_orders():
         check_pencil(A0, B0, got, oracle.basic_ht(A0, B0)[:4])
 
 
+def test_batched_pencil_stats():
+    """Per-pencil device timestamps and counters: every pencil has a start no
+    later than its end, at least one panel when n > 2 and none otherwise, and
+    a forced-failure run (no refinement steps allowed, zero tolerance) needs a
+    panel per reduced column."""
+    sizes = [2, 5, 40, 120]
+    pencils = [inputs.random_pencil(n, seed=900 + n) for n in sizes]
+    for kw, strict in (({}, False), ({"max_ir": 0, "ir_tol_factor": 0.0}, True)):
+        print("ht_batched_pencil_stats sizes=%s %s" % (sizes, kw), flush=True)
+        As, Bs = to_dev(pencils)
+        Qs = [htred.colmajor_empty(A.shape[0]) for A in As]
+        Zs = [htred.colmajor_empty(A.shape[0]) for A in As]
+        plan = htred.BatchedPlan(As, Bs, Qs, Zs, **kw)
+        plan.run()
+        st = plan.pencil_stats().numpy()
+        assert (plan.info.cpu().numpy()[:len(sizes)] == 0).all()
+        assert st.shape == (len(sizes), 8)
+        assert (st[:, 0] >= 0).all() and (st[:, 1] >= st[:, 0]).all()
+        # phase times are parts of the pencil's span
+        assert (st[:, 4:7] >= 0).all() and (st[:, 4:7].sum(axis=1) <= st[:, 1] - st[:, 0]).all()
+        for n, (t0, t1, panels, ir) in zip(sizes, st[:, :4]):
+            if n <= 2:
+                assert panels == 0 and ir == 0
+            elif strict:
+                # the second column of a panel fails unless its residual is
+                # exactly zero, so nearly every panel reduces one column
+                assert (n - 2) // 2 < panels <= n - 2 and ir == 0, (n, panels, ir)
+            else:
+                assert 1 <= panels <= n - 2 and ir >= 0
+
+
 def test_batched_edge_orders():
     sizes = [0, 1, 2, 3, 2, 1]
     pencils = [inputs.random_pencil(n, seed=40 + i) for i, n in enumerate(sizes)]
