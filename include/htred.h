@@ -51,8 +51,17 @@ typedef enum {
     HT_QZ_NONE = 2        /* not computed (pointer may be NULL) */
 } ht_qz_mode;
 
-/* Arithmetic of the trailing block-reflector updates (absorption, Sec. 3.3).
- * Panel reduction, solves and factorisations are always native FP64. */
+/* Arithmetic of the trailing block-reflector updates (absorption, Sec. 3.3:
+ * the window applications and rank-k corrections).  Panel reduction, solves,
+ * chain factorisations and the T/S factors are always native FP64.
+ * The split forms emulate each FP64 product with n_slices fixed-point digit
+ * slices per operand (per-row / per-column power-of-two exponents over
+ * chunks of 32 contraction indices) multiplied on the low-precision matrix
+ * cores with exact FP32 accumulation and recombined in FP64:
+ *   BF16: 7-bit digits, n_slices 1..8, default 8 (56 bits);
+ *   FP8:  4-bit digits, n_slices 1..14, default 14 (56 bits).
+ * Per entry the error is about (n_slices + 3) 2^{-bits n_slices} times
+ * |op(A)| |op(B)|.  ht_reduce_batched supports HT_PREC_FP64 only. */
 typedef enum {
     HT_PREC_FP64 = 0,        /* native FP64 (MFMA) */
     HT_PREC_SPLIT_BF16 = 1,  /* FP64 emulated with BF16 slices, FP32 accumulate */
@@ -182,6 +191,22 @@ int ht_reduce_batched(int32_t batch, const int32_t *n_dev,
  * HT_ERR_HIP if the copy fails.  Meaningless before the batched call ran.
  */
 int ht_batched_pencil_stats(const void *workspace, int32_t batch, int64_t *out, void *stream);
+
+/*
+ * ht_wy_gemm -- one product of the WY updates as ht_reduce computes it for
+ * `prec`:  C = alpha op(A) op(B) + beta C  (op(X) = X or X^T per transA /
+ * transB != 0), op(A) m x k, op(B) k x n, C m x n; device pointers,
+ * column-major, FP64 storage; beta == 0 ignores C's contents.  Exposed so
+ * that the split products can be validated on their own.  n_slices as in
+ * ht_options (0 = default).  Asynchronous on `stream`.  Returns -1 for an
+ * unknown prec, -2 for n_slices out of range, -5/-6/-7 for negative m/n/k,
+ * -10/-12/-15 for a leading dimension below the stored rows, -9/-11/-14
+ * for a NULL operand with non-empty shape.
+ */
+int ht_wy_gemm(int32_t prec, int32_t n_slices, int32_t transA, int32_t transB,
+               int64_t m, int64_t n, int64_t k, double alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb,
+               double beta, double *C, int64_t ldc, void *stream);
 
 /* Human-readable name of a return code. */
 const char *ht_strerror(int code);

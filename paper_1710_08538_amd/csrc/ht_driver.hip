@@ -210,14 +210,27 @@ struct Ctx {
   int64_t cols_extra_ir = 0, ir_steps = 0, ir_failures = 0, absorptions = 0, columns = 0;
 };
 
+// A product of the WY updates (the absorption's window applications and
+// rank-k corrections): FP64 MFMA, or the emulated-FP64 split product of the
+// precision form.  Panels, solves, chains and the T/S factors never come
+// here.
+void wy(Ctx& c, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
+        const double* B, int ldb, double beta, double* C, int ldc) {
+  if (c.opt.prec == HT_PREC_FP64)
+    gemm(c.st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  else
+    split_gemm(c.st, c.opt.prec == HT_PREC_SPLIT_BF16 ? 0 : 1, c.opt.n_slices, ta, tb, m, n, k,
+               alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
 // X(0:rows, window) <- X (I - V W^T), window width wdt, k reflectors (V, W
 // with leading dimension ldv).
 void right_apply(Ctx& c, double* X, int ld, int rows, int wdt, int k, const double* Vf,
                  const double* Wf, int ldv) {
   if (rows <= 0 || wdt <= 0 || k <= 0) return;
   const int pi = c.prof.begin(c.st, HT_PROF_WY);
-  gemm(c.st, false, false, rows, k, wdt, 1.0, X, ld, Vf, ldv, 0.0, c.w->P, c.n);
-  gemm(c.st, false, true, rows, wdt, k, -1.0, c.w->P, c.n, Wf, ldv, 1.0, X, ld);
+  wy(c, false, false, rows, k, wdt, 1.0, X, ld, Vf, ldv, 0.0, c.w->P, c.n);
+  wy(c, false, true, rows, wdt, k, -1.0, c.w->P, c.n, Wf, ldv, 1.0, X, ld);
   c.prof.end(c.st, pi, 4.0 * rows * (double)wdt * k);
   c.flops += 4.0 * rows * (double)wdt * k;
 }
@@ -227,8 +240,8 @@ void left_apply(Ctx& c, double* X, int ld, int ncols, int wdt, int k, const doub
                 const double* Wf, int ldv) {
   if (ncols <= 0 || wdt <= 0 || k <= 0) return;
   const int pi = c.prof.begin(c.st, HT_PROF_WY);
-  gemm(c.st, true, false, k, ncols, wdt, 1.0, Vf, ldv, X, ld, 0.0, c.w->P, k);
-  gemm(c.st, false, false, wdt, ncols, k, -1.0, Wf, ldv, c.w->P, k, 1.0, X, ld);
+  wy(c, true, false, k, ncols, wdt, 1.0, Vf, ldv, X, ld, 0.0, c.w->P, k);
+  wy(c, false, false, wdt, ncols, k, -1.0, Wf, ldv, c.w->P, k, 1.0, X, ld);
   c.prof.end(c.st, pi, 4.0 * ncols * (double)wdt * k);
   c.flops += 4.0 * ncols * (double)wdt * k;
 }
@@ -282,7 +295,10 @@ void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, 
   size_t i = 0;
   while (i < wins.size()) {
     const Win& w0 = wins[i];
-    const bool full = sweep_supported(K) && jobs.size() <= 4 && full_win(w0);
+    // the fused sweep is FP64 only; the precision form applies windows one
+    // at a time through split products
+    const bool full = c.opt.prec == HT_PREC_FP64 && sweep_supported(K) && jobs.size() <= 4 &&
+                      full_win(w0);
     size_t e = i + 1;
     int dir = 0;
     if (full) {
@@ -489,17 +505,17 @@ void absorb(Ctx& c, int s, int k) {
     if (rt.rows <= 0) continue;
     double* Xs = at(rt.X, rt.ld, 0, s + 1);
     double* Xe = at(rt.X, rt.ld, 0, n - k);
-    gemm(c.st, false, false, rt.rows, k, k, 1.0, Xs, rt.ld, V1, n, 0.0, w.Wk, n);
-    gemm(c.st, false, false, rt.rows, k, k, 1.0, Xe, rt.ld, L1, n, 1.0, w.Wk, n);
-    gemm(c.st, false, false, rt.rows, k, k, 1.0, w.Wk, n, w.T, c.nb, 0.0, w.P, n);
-    gemm(c.st, false, true, rt.rows, k, k, -1.0, w.P, n, V1, n, 1.0, Xs, rt.ld);
-    gemm(c.st, false, true, rt.rows, k, k, -1.0, w.P, n, L1, n, 1.0, Xe, rt.ld);
+    wy(c, false, false, rt.rows, k, k, 1.0, Xs, rt.ld, V1, n, 0.0, w.Wk, n);
+    wy(c, false, false, rt.rows, k, k, 1.0, Xe, rt.ld, L1, n, 1.0, w.Wk, n);
+    wy(c, false, false, rt.rows, k, k, 1.0, w.Wk, n, w.T, c.nb, 0.0, w.P, n);
+    wy(c, false, true, rt.rows, k, k, -1.0, w.P, n, V1, n, 1.0, Xs, rt.ld);
+    wy(c, false, true, rt.rows, k, k, -1.0, w.P, n, L1, n, 1.0, Xe, rt.ld);
     c.flops += 10.0 * rt.rows * (double)k * k;
   }
   // rows s+1..n-1 of A through Y = A V T (Sec. 3.3.1 e):
   //   A(:, j+1:n) <- A Q^;  A(:, j) -= Y V1(k-1,:)^T;  A(:, n-k:n) -= Y L1^T.
   gemv_n(c.st, L, k, -1.0, w.Y, n, w.V + (k - 1), n, 1.0, at(A, lda, s + 1, j), w.partials);
-  gemm(c.st, false, true, L, k, k, -1.0, w.Y, n, L1, n, 1.0, at(A, lda, s + 1, n - k), lda);
+  wy(c, false, true, L, k, k, -1.0, w.Y, n, L1, n, 1.0, at(A, lda, s + 1, n - k), lda);
   c.flops += 4.0 * L * (double)k * k;
 
   // (3.3.1 e) restore B by RQ decompositions, bottom to top: the k x (w)
@@ -521,9 +537,9 @@ void absorb(Ctx& c, int s, int k) {
 
   // (3.3.2 c) spike columns s+1..j of B:
   //   B(s+1:j+1, s+1:j+1) -= U1 S^T (U^T B(s+1:n, s+1:j+1));  B(j+1:n, s+1:j+1) = 0.
-  gemm(c.st, true, false, k, k, L, 1.0, w.U, n, at(B, ldb, s + 1, s + 1), ldb, 0.0, w.Kt, k);
-  gemm(c.st, true, false, k, k, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
-  gemm(c.st, false, false, k, k, k, -1.0, w.U, n, w.Kt2, k, 1.0, at(B, ldb, s + 1, s + 1), ldb);
+  wy(c, true, false, k, k, L, 1.0, w.U, n, at(B, ldb, s + 1, s + 1), ldb, 0.0, w.Kt, k);
+  wy(c, true, false, k, k, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+  wy(c, false, false, k, k, k, -1.0, w.U, n, w.Kt2, k, 1.0, at(B, ldb, s + 1, s + 1), ldb);
   zero_mat(c.st, at(B, ldb, j + 1, s + 1), mp, k, ldb);
   // Fact 3: columns s+1..j are now triangular; their entries below the
   // diagonal are rounding noise of the opposite reflectors (Lemma 2.1) and are
@@ -538,22 +554,22 @@ void absorb(Ctx& c, int s, int k) {
   {
     const int ncb = n - j - 1, nca = n - j;
     double* Bs = at(B, ldb, s + 1, j + 1);
-    gemm(c.st, true, false, k, ncb, 2 * k, 1.0, w.Ucat, 2 * k, Bs, ldb, 0.0, w.Kt, k);
-    gemm(c.st, true, false, k, ncb, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
-    gemm(c.st, false, false, 2 * k, ncb, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, Bs, ldb);
+    wy(c, true, false, k, ncb, 2 * k, 1.0, w.Ucat, 2 * k, Bs, ldb, 0.0, w.Kt, k);
+    wy(c, true, false, k, ncb, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+    wy(c, false, false, 2 * k, ncb, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, Bs, ldb);
     double* As = at(A, lda, s + 1, j);
-    gemm(c.st, true, false, k, nca, 2 * k, 1.0, w.Ucat, 2 * k, As, lda, 0.0, w.Kt, k);
-    gemm(c.st, true, false, k, nca, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
-    gemm(c.st, false, false, 2 * k, nca, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, As, lda);
+    wy(c, true, false, k, nca, 2 * k, 1.0, w.Ucat, 2 * k, As, lda, 0.0, w.Kt, k);
+    wy(c, true, false, k, nca, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+    wy(c, false, false, 2 * k, nca, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, As, lda);
     c.flops += 10.0 * (double)k * k * (nca + ncb);
   }
   // (3.3.2 d) Q(:, j+1:n) <- Q Q~;  W = Q(:, s+1:j+k+1) Ucat;  Q(:, s+1:..) -= W S Ucat^T.
   if (c.wantQ) {
     sweep_cols_right(c, c.Q, c.ldq, n, j, bl, 2);
     double* Qs = at(c.Q, c.ldq, 0, s + 1);
-    gemm(c.st, false, false, n, k, 2 * k, 1.0, Qs, c.ldq, w.Ucat, 2 * k, 0.0, w.Wk, n);
-    gemm(c.st, false, false, n, k, k, 1.0, w.Wk, n, w.S, c.nb, 0.0, w.P, n);
-    gemm(c.st, false, true, n, 2 * k, k, -1.0, w.P, n, w.Ucat, 2 * k, 1.0, Qs, c.ldq);
+    wy(c, false, false, n, k, 2 * k, 1.0, Qs, c.ldq, w.Ucat, 2 * k, 0.0, w.Wk, n);
+    wy(c, false, false, n, k, k, 1.0, w.Wk, n, w.S, c.nb, 0.0, w.P, n);
+    wy(c, false, true, n, 2 * k, k, -1.0, w.P, n, w.Ucat, 2 * k, 1.0, Qs, c.ldq);
     c.flops += 10.0 * (double)n * k * k;
   }
 
@@ -702,6 +718,12 @@ static int resolve_opts(const ht_options* in, ht_options* out) {
   if (out->max_ir < 0) return -10;
   if (out->qmode < 0 || out->qmode > 2 || out->zmode < 0 || out->zmode > 2) return -10;
   if (!(out->ir_tol_factor >= 0.0)) return -10;
+  if (out->prec < HT_PREC_FP64 || out->prec > HT_PREC_SPLIT_FP8) return -10;
+  if (out->prec != HT_PREC_FP64) {
+    const int fmt = out->prec == HT_PREC_SPLIT_BF16 ? 0 : 1;
+    if (out->n_slices == 0) out->n_slices = split_default_slices(fmt);
+    if (out->n_slices < 1 || out->n_slices > split_max_slices(fmt)) return -10;
+  }
   return 0;
 }
 
@@ -729,7 +751,6 @@ int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda
   if (n > 0 && (!A || !B)) return !A ? -1 : -2;
   if (n > 0 && wantQ && !Q) return -3;
   if (n > 0 && wantZ && !Z) return -4;
-  if (o.prec != HT_PREC_FP64) return HT_ERR_UNSUPPORTED;
   if (o.qmode == HT_QZ_ACCUMULATE || o.zmode == HT_QZ_ACCUMULATE) return HT_ERR_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   if (stats) memset(stats, 0, sizeof(*stats));
@@ -887,6 +908,37 @@ int ht_batched_pencil_stats(const void* workspace, int32_t batch, int64_t* out, 
     o[7] = 0;
   }
   return HT_OK;
+}
+
+int ht_wy_gemm(int32_t prec, int32_t n_slices, int32_t transA, int32_t transB, int64_t m,
+               int64_t n, int64_t k, double alpha, const double* A, int64_t lda, const double* B,
+               int64_t ldb, double beta, double* C, int64_t ldc, void* stream) {
+  if (prec < HT_PREC_FP64 || prec > HT_PREC_SPLIT_FP8) return -1;
+  const int fmt = prec == HT_PREC_SPLIT_BF16 ? 0 : 1;
+  int ns = n_slices;
+  if (prec != HT_PREC_FP64) {
+    if (ns == 0) ns = split_default_slices(fmt);
+    if (ns < 1 || ns > split_max_slices(fmt)) return -2;
+  }
+  if (m < 0 || m > INT32_MAX) return -5;
+  if (n < 0 || n > INT32_MAX) return -6;
+  if (k < 0 || k > INT32_MAX) return -7;
+  const int64_t ra = transA ? k : m, rb = transB ? n : k;
+  if (lda < std::max<int64_t>(1, ra)) return -10;
+  if (ldb < std::max<int64_t>(1, rb)) return -12;
+  if (ldc < std::max<int64_t>(1, m)) return -15;
+  if (m == 0 || n == 0) return HT_OK;
+  if (k > 0 && !A) return -9;
+  if (k > 0 && !B) return -11;
+  if (!C) return -14;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == HT_PREC_FP64)
+    htk::gemm(st, transA != 0, transB != 0, (int)m, (int)n, (int)k, alpha, A, (int)lda, B,
+              (int)ldb, beta, C, (int)ldc);
+  else
+    htk::split_gemm(st, fmt, ns, transA != 0, transB != 0, (int)m, (int)n, (int)k, alpha, A,
+                    (int)lda, B, (int)ldb, beta, C, (int)ldc);
+  return hipGetLastError() == hipSuccess ? HT_OK : HT_ERR_HIP;
 }
 
 }  // extern "C"

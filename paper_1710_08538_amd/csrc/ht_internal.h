@@ -17,6 +17,17 @@ void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k,
           double alpha, const double* A, int lda, const double* B, int ldb,
           double beta, double* C, int ldc);
 
+// Emulated-FP64 product with the same contract as gemm, formed from ns
+// fixed-point digit slices per operand on the low-precision matrix cores:
+// fmt 0 = BF16 digits (7 bits, ns <= 8), fmt 1 = FP8 E4M3 digits (4 bits,
+// ns <= 14).  Error below (ns + 5) 2^{-b ns} 2^{e_row + e_col} per
+// contraction index (exponents per row / column and chunk of 32 indices).
+void split_gemm(hipStream_t st, int fmt, int ns, bool transA, bool transB, int m, int n, int k,
+                double alpha, const double* A, int lda, const double* B, int ldb, double beta,
+                double* C, int ldc);
+int split_max_slices(int fmt);
+int split_default_slices(int fmt);
+
 // y(0:m) = alpha * X(0:m, 0:k) * x + beta * y; x has stride incx.
 // `partials` must hold ceil(k/512)*m doubles when k > 256.
 void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,

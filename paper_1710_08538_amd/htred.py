@@ -78,6 +78,10 @@ def lib():
         L.ht_reduce_batched.restype = ctypes.c_int
         L.ht_batched_pencil_stats.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.ht_batched_pencil_stats.restype = ctypes.c_int
+        L.ht_wy_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                 i64, i64, i64, ctypes.c_double, vp, i64, vp, i64,
+                                 ctypes.c_double, vp, i64, vp]
+        L.ht_wy_gemm.restype = ctypes.c_int
         L.ht_strerror.argtypes = [ctypes.c_int]
         L.ht_strerror.restype = ctypes.c_char_p
         L.ht_version.argtypes = []
@@ -127,8 +131,8 @@ def _check(rc):
 
 
 def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
-           prec=HT_PREC_FP64, stats=False, workspace=None, stream=None, check_finite=False,
-           profile=False, solve_solo=False):
+           prec=HT_PREC_FP64, n_slices=0, stats=False, workspace=None, stream=None,
+           check_finite=False, profile=False, solve_solo=False):
     """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
 
     A, B: n x n column-major float64 GPU tensors (B upper triangular).
@@ -144,7 +148,7 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
         Z = colmajor_empty(n, device=A.device)
     ldq, ldz = _ld(Q, n, "Q"), _ld(Z, n, "Z")
     o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
-                flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
+                n_slices=n_slices, flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
                 | (HT_FLAG_PROFILE if profile else 0)
                 | (HT_FLAG_SOLVE_SOLO if solve_solo else 0))
     st = Stats()
@@ -225,6 +229,40 @@ def reduce_batched(As, Bs, Qs=None, Zs=None, **kw):
     plan = BatchedPlan(As, Bs, Qs, Zs, **kw)
     plan.run()
     return Qs, Zs, plan.info[:len(As)].clone()
+
+
+def _colmajor_ld(t, rows, cols, name):
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("%s must be a float64 GPU tensor" % name)
+    if tuple(t.shape) != (rows, cols):
+        raise ValueError("%s must be %dx%d" % (name, rows, cols))
+    if rows > 0 and cols > 0 and t.stride(0) != 1:
+        raise ValueError("%s must be column-major (stride(0) == 1)" % name)
+    return max(t.stride(1) if cols > 1 else rows, rows, 1)
+
+
+def wy_gemm(A, B, C=None, transA=False, transB=False, alpha=1.0, beta=0.0, prec=HT_PREC_FP64,
+            n_slices=0, stream=None):
+    """One WY-update product as ht_reduce forms it for `prec`:
+    C = alpha op(A) op(B) + beta C on column-major float64 GPU tensors.
+    Returns C (allocated when None)."""
+    ra, ca = A.shape
+    rb, cb = B.shape
+    m, k = (ca, ra) if transA else (ra, ca)
+    k2, n = (cb, rb) if transB else (rb, cb)
+    if k != k2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (k, k2))
+    lda = _colmajor_ld(A, ra, ca, "A")
+    ldb = _colmajor_ld(B, rb, cb, "B")
+    if C is None:
+        C = colmajor_empty(m, n, device=A.device)
+        beta = 0.0
+    ldc = _colmajor_ld(C, m, n, "C")
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    _check(lib().ht_wy_gemm(prec, n_slices, int(transA), int(transB), m, n, k, alpha,
+                            A.data_ptr(), lda, B.data_ptr(), ldb, beta, C.data_ptr(), ldc,
+                            s.cuda_stream))
+    return C
 
 
 def workspace_size(n, nb=64):

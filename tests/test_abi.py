@@ -86,3 +86,52 @@ def test_batched_argument_validation(L):
                                ctypes.byref(o), None, 0, None) == 0
     assert L.ht_reduce_batched(3, None, None, None, None, None, None, None, 64,
                                ctypes.byref(o), None, 0, None) == -2
+
+
+def test_wy_gemm_argument_validation(L):
+    z = ctypes.c_void_p(0)
+    args = lambda prec=0, ns=0, m=4, n=4, k=4, lda=4, ldb=4, ldc=4, ta=0, tb=0: (
+        prec, ns, ta, tb, m, n, k, 1.0, z, lda, z, ldb, 0.0, z, ldc, z)
+    assert L.ht_wy_gemm(*args(prec=3)) == -1
+    assert L.ht_wy_gemm(*args(prec=1, ns=9)) == -2
+    assert L.ht_wy_gemm(*args(prec=2, ns=15)) == -2
+    assert L.ht_wy_gemm(*args(prec=1, ns=-1)) == -2
+    assert L.ht_wy_gemm(*args(m=-1)) == -5
+    assert L.ht_wy_gemm(*args(n=-1)) == -6
+    assert L.ht_wy_gemm(*args(k=-1)) == -7
+    assert L.ht_wy_gemm(*args(lda=3)) == -10
+    assert L.ht_wy_gemm(*args(ta=1, m=8, lda=4, ldc=8)) == -9  # A^T is k x m: lda 4 suffices
+    assert L.ht_wy_gemm(*args(ta=1, k=8, lda=4)) == -10
+    assert L.ht_wy_gemm(*args(ldb=3)) == -12
+    assert L.ht_wy_gemm(*args(tb=1, n=8, ldb=4)) == -12
+    assert L.ht_wy_gemm(*args(ldc=3)) == -15
+    assert L.ht_wy_gemm(*args(m=0)) == 0  # empty: no pointer needed
+    assert L.ht_wy_gemm(*args()) == -9    # NULL A with a non-empty product
+
+
+def test_split_precision_options(L):
+    from paper_1710_08538_amd import htred
+    for prec, ok, bad in ((htred.HT_PREC_SPLIT_BF16, (0, 1, 8), (9, -1)),
+                          (htred.HT_PREC_SPLIT_FP8, (0, 1, 14), (15,))):
+        for ns in ok:
+            o = htred.options(prec=prec, n_slices=ns)
+            assert L.ht_workspace_size(100, ctypes.byref(o)) > 0
+        for ns in bad:
+            o = htred.options(prec=prec, n_slices=ns)
+            assert L.ht_workspace_size(100, ctypes.byref(o)) == 0
+    o = htred.options(prec=3)
+    assert L.ht_workspace_size(100, ctypes.byref(o)) == 0
+    # the batched form is FP64 only
+    o = htred.options(prec=htred.HT_PREC_SPLIT_BF16)
+    one = (ctypes.c_int32 * 1)(8)
+    ptr = (ctypes.c_void_p * 1)(8)
+    info = (ctypes.c_int32 * 1)(0)
+    assert L.ht_reduce_batched(1, one, ptr, ptr, ptr, ptr, one, info, 8, ctypes.byref(o),
+                               None, 0, None) == htred_unsupported(L)
+
+
+def htred_unsupported(L):
+    for code in range(1, 10):
+        if b"unsupported" in L.ht_strerror(code):
+            return code
+    raise AssertionError("no unsupported-option code")
