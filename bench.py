@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "HT reduction GFLOP/s + time at n=16384 FP64 (vs split-prec/batched), backward err"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 
 
 def nominal_flops(n):
@@ -135,10 +137,32 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
             "backward_error_max": worst}
 
 
+def precision_form(torch, htred, checks, A0d, B0d, A, B, Q, Z, ws, nb, name, t_fp64):
+    """The precision form on the headline pencil: the WY products as
+    emulated-FP64 split products (default slice count of the format), every
+    other step native FP64; one run, timed, with its backward errors."""
+    prec = {"bf16": htred.HT_PREC_SPLIT_BF16, "fp8": htred.HT_PREC_SPLIT_FP8}[name]
+    n = A0d.shape[0]
+    A.copy_(A0d)
+    B.copy_(B0d)
+    torch.cuda.synchronize()
+    t = time.time()
+    st = htred.reduce(A, B, Q, Z, nb=nb, prec=prec, stats=True, workspace=ws)[2]
+    torch.cuda.synchronize()
+    dt = time.time() - t
+    inv = checks.invariants(A0d, B0d, A, B, Q, Z)
+    return {"n": n, "nb": nb, "digits": name, "n_slices": {"bf16": 8, "fp8": 14}[name],
+            "time_s": dt, "gflops_nominal": nominal_flops(n) / dt / 1e9,
+            "time_vs_fp64": dt / t_fp64,
+            "backward_error": {k: float(inv[k]) for k in ("bwd_A", "bwd_B", "orth_Q", "orth_Z")},
+            "invariants_ok": bool(checks.invariants_ok(inv, n)),
+            "absorptions": st["absorptions"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n16384")
     ap.add_argument("--n", type=int, default=None, help="override the order (same generator)")
@@ -148,7 +172,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched form measured beside the headline run")
+                    help="skip the precision and batched forms measured beside the headline run")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -222,6 +246,13 @@ def main():
         elif name == "sweep":                  # FP64 MFMA
             a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
             r = {"bound": "mfma", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
+        elif name == "wy" and prec != htred.HT_PREC_FP64:
+            # split products: every FP64 flop costs ns(ns+1)/2 digit-pair
+            # products on the BF16 / FP8 matrix cores
+            ns = 8 if prec == htred.HT_PREC_SPLIT_BF16 else 14
+            a = prof_work[c] * ns * (ns + 1) / 2 / (prof_ms[c] * 1e-3) / 1e12
+            pk = PEAK_BF16_TFLOPS if prec == htred.HT_PREC_SPLIT_BF16 else PEAK_FP8_TFLOPS
+            r = {"bound": "mfma", "achieved": a, "peak": pk, "unit": "TFLOP/s"}
         else:                                  # chains, generic products: FP64 vector ALU
             a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
             r = {"bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
@@ -267,11 +298,19 @@ def main():
         result["backward_error"] = {k: inv[k] for k in ("bwd_A", "bwd_B", "orth_Q", "orth_Z",
                                                        "zeros_H", "zeros_T")}
         result["invariants_ok"] = bool(checks.invariants_ok(inv, n))
+    if not args.no_forms:
+        result["forms"] = {}
+        if prec == htred.HT_PREC_FP64:
+            for name in ("bf16", "fp8"):
+                print("bench: precision form %s ..." % name, file=sys.stderr, flush=True)
+                result["forms"]["precision_" + name] = precision_form(
+                    torch, htred, checks, A0d, B0d, A, B, Q, Z, ws, args.nb, name,
+                    ms_per_step / 1000.0)
     del A0d, B0d, A, B, Q, Z, ws
     torch.cuda.empty_cache()
     if not args.no_forms:
         print("bench: batched form ...", file=sys.stderr, flush=True)
-        result["forms"] = {"batched": batched_form(torch, htred, inputs, checks)}
+        result["forms"]["batched"] = batched_form(torch, htred, inputs, checks)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         print("bench: cpu baseline ...", file=sys.stderr, flush=True)
