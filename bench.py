@@ -21,6 +21,7 @@ first columns of the same pencil, extrapolated to the whole reduction by its
 per-column rotation count.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -135,6 +136,33 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
                                      if big.any() else None),
             "checked_sample": len(range(0, count, 32)), "invariants_ok": ok,
             "backward_error_max": worst}
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "hbm_traffic.json")
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of the kernel class `cls` from the committed PMC
+    counts (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
+    known size), or None if there are none or the kernel's source changed
+    since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = table.get("classes", {}).get(cls)
+    if not ent:
+        return None
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), ent["source"])
+    try:
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != ent["source_sha256"]:
+                return None
+    except OSError:
+        return None
+    return ent["bytes_per_launch"]
 
 
 def precision_form(torch, htred, checks, A0d, B0d, A, B, Q, Z, ws, nb, name, t_fp64):
@@ -257,7 +285,7 @@ def main():
             a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
             r = {"bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
         r["frac"] = r["achieved"] / r["peak"]
-        r["traffic"] = None
+        r["traffic"] = measured_traffic(name)
         r["kernel_class"] = name
         r["launches_per_step"] = prof_l[c]
         r["avg_launch_us"] = 1000.0 * prof_ms[c] / max(prof_l[c], 1)
