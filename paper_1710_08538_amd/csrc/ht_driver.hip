@@ -278,12 +278,15 @@ std::vector<Win> left_windows(const Blocks& bl, int chain) {
 struct RJob { double* X; int ld; int rows; bool tri; int tri_off; };
 
 // Apply the windows of a chain, in order, as right multiplications
-// X(:, j+1+win) <- X(:, j+1+win) (I - V W^T) to every job.  Runs of
-// consecutive full windows (width 2k, moving by k) go to the fused MFMA
-// sweep kernel in one launch for all jobs; the odd windows at the ends of a
-// chain (first window p+k wide, last one p x p) use the generic product.
+// X(:, j+1+win) <- X(:, j+1+win) (I - V W^T) to every job, or with `left`
+// as left multiplications X(j+1+win, :) <- (I - V W^T)^T X(j+1+win, :) to
+// the columns of every job (job.X at its first column, rows = its number of
+// columns, tri_off = that column's index).  Runs of consecutive full windows
+// (width 2k, moving by k) go to the fused MFMA sweep kernel in one launch
+// for all jobs; the odd windows at the ends of a chain (first window p+k
+// wide, last one p x p) use the generic product.
 void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, int chain,
-                const std::vector<Win>& wins) {
+                const std::vector<Win>& wins, bool left = false) {
   const int s = bl.s, K = bl.s;
   // a full window: its 2s-wide slot window (the real window plus zero
   // padding) lies inside the trailing part; consecutive full windows move by s
@@ -333,14 +336,18 @@ void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, 
       double fl = 0.0;  // algorithmic: 4 rows wdt nrefl per window
       for (const RJob& jb : jobs) {
         if (jb.rows <= 0) continue;
-        for (size_t t = i; t < e; ++t) {  // B: rows below a window's end are zero
-          const int r = jb.tri ? std::max(0, std::min(jb.rows, j + 1 + wins[t].a + wins[t].wdt - jb.tri_off))
-                               : jb.rows;
+        for (size_t t = i; t < e; ++t) {
+          // B: right, rows below a window's end are zero; left, columns
+          // left of a window's start
+          const int ws = j + 1 + wins[t].a;
+          const int r = !jb.tri ? jb.rows
+                        : left ? jb.rows - std::min(jb.rows, std::max(0, ws - jb.tri_off))
+                               : std::max(0, std::min(jb.rows, ws + wins[t].wdt - jb.tri_off));
           fl += 4.0 * r * (double)wins[t].wdt * wins[t].k;
         }
       }
       const int pi = c.prof.begin(c.st, HT_PROF_SWEEP);
-      sweep_rows(c.st, sa, K, dir);
+      sweep_rows(c.st, sa, K, dir, left);
       c.prof.end(c.st, pi, fl);
       c.flops += fl;
       i = e;
@@ -348,6 +355,12 @@ void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, 
     }
     for (const RJob& jb : jobs) {
       if (jb.rows <= 0) continue;
+      if (left) {
+        const int cs = jb.tri ? std::min(jb.rows, std::max(0, j + 1 + w0.a - jb.tri_off)) : 0;
+        left_apply(c, at(jb.X, jb.ld, j + 1 + w0.a, cs), jb.ld, jb.rows - cs, w0.wdt, w0.k,
+                   tV(*c.w, chain, w0, s), tW(*c.w, chain, w0, s), 2 * s);
+        continue;
+      }
       const int r = jb.tri ? std::min(jb.rows, j + 1 + w0.a + w0.wdt - jb.tri_off) : jb.rows;
       right_apply(c, at(jb.X, jb.ld, 0, j + 1 + w0.a), jb.ld, r, w0.wdt, w0.k,
                   tV(*c.w, chain, w0, s), tW(*c.w, chain, w0, s), 2 * s);
@@ -365,11 +378,8 @@ void sweep_right(Ctx& c, double* X, int ld, int rows, bool tri, int j, const Blo
 // Left sweep of a chain over rows j+1.. of X, columns [c0, n).  With
 // `tri`, columns left of a window's first row are zero and skipped.
 void sweep_left(Ctx& c, double* X, int ld, int c0, bool tri, int j, const Blocks& bl, int chain) {
-  for (const Win& wn : left_windows(bl, chain)) {
-    const int cs = tri ? std::max(c0, j + 1 + wn.a) : c0;
-    left_apply(c, at(X, ld, j + 1 + wn.a, cs), ld, c.n - cs, wn.wdt, wn.k,
-               tV(*c.w, chain, wn, bl.s), tW(*c.w, chain, wn, bl.s), 2 * bl.s);
-  }
+  sweep_jobs(c, {RJob{at(X, ld, 0, c0), ld, c.n - c0, tri, c0}}, j, bl, chain,
+             left_windows(bl, chain), true);
 }
 
 // Q(:, j+1 : n) <- Q * (chain transforms in order).
@@ -548,8 +558,9 @@ void absorb(Ctx& c, int s, int k) {
   c.flops += 2.0 * k * (double)k * (L + 2 * k);
 
   // (3.3.2 c, e) rows j+1..n-1: B(:, j+1:n) and A(:, j:n) <- Q~^T (.)
-  sweep_left(c, B, ldb, j + 1, true, j, bl, 2);
-  sweep_left(c, A, lda, j, false, j, bl, 2);
+  sweep_jobs(c, {RJob{at(B, ldb, 0, j + 1), ldb, n - j - 1, true, j + 1},
+                 RJob{at(A, lda, 0, j), lda, n - j, false, j}},
+             j, bl, 2, left_windows(bl, 2), true);
   // corrections with Ucat = [U1; R1] on rows s+1..j+k:  X -= Ucat S^T (Ucat^T X)
   {
     const int ncb = n - j - 1, nca = n - j;

@@ -8,9 +8,9 @@ namespace htk {
 struct SweepJob {
   double* X;     // row 0 of the job (column indices are absolute)
   int ld;
-  int nrows;     // rows 0 .. nrows-1
+  int nrows;     // rows 0 .. nrows-1 (columns, for a transposed sweep)
   int tri;       // 1: X is upper triangular in global indices (skip zero windows)
-  int tri_off;   // global row index of the job's row 0
+  int tri_off;   // global row (column, transposed) index of the job's row 0
   int wg0;       // first workgroup of this job in the launch
 };
 
@@ -27,7 +27,9 @@ struct SweepArgs {
 
 bool sweep_supported(int k);
 // X(:, win) <- X(:, win) - (X(:, win) V) W^T for every window in order;
-// dir = +1 (windows move right) or -1 (left).
-void sweep_rows(hipStream_t st, const SweepArgs& args, int k, int dir);
+// dir = +1 (windows move right) or -1 (left).  trans: sweep X^T instead,
+// i.e. X(win, :) <- X(win, :) - W (V^T X(win, :)) over slabs of columns
+// (job.X at the job's first column, window indices = absolute rows).
+void sweep_rows(hipStream_t st, const SweepArgs& args, int k, int dir, bool trans = false);
 
 }  // namespace htk

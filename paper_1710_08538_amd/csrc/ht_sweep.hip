@@ -81,7 +81,11 @@ struct WReg {
   }
 };
 
-template <int K, int DIR>
+// TR = 1: the sweep of X^T, i.e. the left application
+//   X(win, :) <- (I - V W^T)^T X(win, :) = X(win, :) - W (V^T X(win, :))
+// on slabs of 64 columns of X: "rows" are columns of X (relative to the
+// job's first column) and window "columns" are absolute rows of X.
+template <int K, int DIR, int TR>
 __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
   constexpr int NT = 2 * K / 16;  // window tiles of 16 columns
   constexpr int NP = K / 16;      // tiles of P^T
@@ -102,25 +106,40 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
   const size_t ld = (size_t)job.ld;
   const size_t rowc = (size_t)min(row, job.nrows - 1);
 
-  // first window that is not structurally zero on this slab (upper
-  // triangular X, windows moving right): need column end > first row
-  int t0 = 0;
-  if (job.tri && DIR > 0) {
+  // Windows that are structurally zero on this slab of an upper triangular
+  // X are skipped (applying a transform to zeros leaves zeros).
+  int t0 = 0, tend = a.nwin;
+  if (job.tri && !TR && DIR > 0) {
+    // right sweep: X(r, win) = 0 when the window ends left of row r
     const int need = ra + job.tri_off;  // global row of the slab's first row
     const int q = need - a.c0 - 2 * K;
     if (q >= 0) t0 = q / K + 1;
   }
-  if (t0 >= a.nwin) return;
+  if (job.tri && TR) {
+    // left sweep: X(win, c) = 0 when the window starts below row c, i.e.
+    // below the slab's last column
+    const int last = ra + job.tri_off + 63;
+    if (DIR > 0) {
+      tend = (a.c0 > last) ? 0 : min(a.nwin, (last - a.c0) / K + 1);
+    } else {
+      const int q = a.c0 - last;
+      if (q > 0) t0 = (q + K - 1) / K;
+    }
+  }
+  if (t0 >= tend) return;
 
   v4d xt[NT];
   v4d pre[NH];
   int cs = a.c0 + DIR * t0 * K;  // first column of the current window
 
+  auto at = [&](size_t r, int col) -> size_t {
+    return TR ? (size_t)col + r * ld : r + (size_t)col * ld;
+  };
   auto load_tile = [&](int col0) -> v4d {
     v4d v;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double x = X[rowc + (size_t)(col0 + g + 4 * i) * ld];
+      const double x = X[at(rowc, col0 + g + 4 * i)];
       v[i] = rok ? x : 0.0;
     }
     return v;
@@ -128,14 +147,14 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
   auto store_tile = [&](int col0, const v4d& v) {
     if (rok) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) X[(size_t)row + (size_t)(col0 + g + 4 * i) * ld] = v[i];
+      for (int i = 0; i < 4; ++i) X[at((size_t)row, col0 + g + 4 * i)] = v[i];
     }
   };
 
 #pragma unroll
   for (int t = 0; t < NT; ++t) xt[t] = load_tile(cs + 16 * t);
 
-  for (int w = t0; w < a.nwin; ++w) {
+  for (int w = t0; w < tend; ++w) {
     const double* V = a.Vp + (size_t)(a.slot0 + w * a.slot_step) * (2 * K * K);
     const double* W = a.Wp + (size_t)(a.slot0 + w * a.slot_step) * (2 * K * K);
     // ---- step 1: P^T = V^T X^T
@@ -161,7 +180,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
     }
     // prefetch the columns entering the next window
     const int ncs = cs + DIR * K;
-    if (w + 1 < a.nwin) {
+    if (w + 1 < tend) {
 #pragma unroll
       for (int h = 0; h < NH; ++h)
         pre[h] = load_tile((DIR > 0 ? ncs + K : ncs) + 16 * h);
@@ -184,7 +203,7 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
       __syncthreads();
     }
     // ---- advance: store the leaving half, shift the carry, take the entering half
-    if (w + 1 < a.nwin) {
+    if (w + 1 < tend) {
       if (DIR > 0) {
 #pragma unroll
         for (int h = 0; h < NH; ++h) store_tile(cs + 16 * h, xt[h]);
@@ -206,18 +225,24 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
 
 bool sweep_supported(int k) { return k == 64 || k == 128; }
 
-void sweep_rows(hipStream_t st, const SweepArgs& args, int k, int dir) {
+template <int K>
+void launch_sweep(hipStream_t st, const SweepArgs& args, int grid, int dir, bool trans) {
+  if (trans) {
+    if (dir > 0) hipLaunchKernelGGL((k_sweep_rows<K, 1, 1>), dim3(grid), dim3(256), 0, st, args);
+    else hipLaunchKernelGGL((k_sweep_rows<K, -1, 1>), dim3(grid), dim3(256), 0, st, args);
+  } else {
+    if (dir > 0) hipLaunchKernelGGL((k_sweep_rows<K, 1, 0>), dim3(grid), dim3(256), 0, st, args);
+    else hipLaunchKernelGGL((k_sweep_rows<K, -1, 0>), dim3(grid), dim3(256), 0, st, args);
+  }
+}
+
+void sweep_rows(hipStream_t st, const SweepArgs& args, int k, int dir, bool trans) {
   if (args.nwin <= 0 || args.njobs <= 0) return;
   const int grid = args.job[args.njobs - 1].wg0 +
                    (args.job[args.njobs - 1].nrows + 63) / 64;
   if (grid <= 0) return;
-  if (k == 128) {
-    if (dir > 0) hipLaunchKernelGGL((k_sweep_rows<128, 1>), dim3(grid), dim3(256), 0, st, args);
-    else hipLaunchKernelGGL((k_sweep_rows<128, -1>), dim3(grid), dim3(256), 0, st, args);
-  } else {
-    if (dir > 0) hipLaunchKernelGGL((k_sweep_rows<64, 1>), dim3(grid), dim3(256), 0, st, args);
-    else hipLaunchKernelGGL((k_sweep_rows<64, -1>), dim3(grid), dim3(256), 0, st, args);
-  }
+  if (k == 128) launch_sweep<128>(st, args, grid, dir, trans);
+  else launch_sweep<64>(st, args, grid, dir, trans);
 }
 
 }  // namespace htk
