@@ -334,11 +334,14 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
     if (threadIdx.x < 4) a.ctl[4 * ((a.epoch + 1) & 1) + threadIdx.x] = 0;
     if (wave == 0) {
       // ---- substitution wavefront ----
-      double rhs2 = 0.0, facc = 0.0, crow;
+      double rhs2 = 0.0, facc = 0.0;
       int e2 = 0, fE = 0, emax = 0;
-      crow = a.c[min(64 * (nb - 1) + lane, a.m - 1)];
+      // right-hand sides are read two blocks ahead, off the critical path
+      double crow = a.c[min(64 * (nb - 1) + lane, a.m - 1)];
+      double crow_next = (nb >= 2) ? a.c[64 * (nb - 2) + lane] : 0.0;
       __syncthreads();  // staged tiles of block nb-1
       for (int b = nb - 1; b >= 0; --b) {
+        const double crow_nn = (b >= 2) ? a.c[64 * (b - 2) + lane] : 0.0;
         const int buf = b & 1;
         const int nr = min(64, a.m - 64 * b);
         const bool live = lane < nr;
@@ -379,7 +382,8 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
         publish_block(a.xll + (size_t)b * kWords, a.epoch, xo, e, lane);
         rhs2 = r2;
         e2 = e;
-        if (b >= 1) crow = a.c[64 * (b - 1) + lane];
+        crow = crow_next;
+        crow_next = crow_nn;
         // the far sum of the next block: complete the loads issued above
         if (want_far) {
           const int rr = b - 1;
@@ -397,9 +401,11 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
               if (__shfl(got, 0, 64)) { own = true; break; }
             }
             __builtin_amdgcn_s_sleep(1);
-            wlo = ld_word(blk + 2 * lane);
-            whi = ld_word(blk + 2 * lane + 1);
             wex = ld_word(blk + 128);
+            if (__all(word_ok(wex, a.epoch))) {  // then the data words
+              wlo = ld_word(blk + 2 * lane);
+              whi = ld_word(blk + 2 * lane + 1);
+            }
           }
           if (own) {
             facc = far_sum_wave(a, rr, nb, lane, fE);
@@ -511,14 +517,19 @@ __global__ __launch_bounds__(kNT) void k_trsv(TrsvArgs a) {
     if (nb - 2 >= cend) load_tile(a, r, nb - 2, lane, wave, tB);
     auto consume = [&](double* t, int cb) {
       if (wave == 0) {
+        // poll the exponent word alone (one address for the whole wavefront)
+        // until it carries this call's epoch, then read the data words, which
+        // were stored before it (re-read until every word is current)
         const uint64_t* blk = a.xll + (size_t)cb * kWords;
-        uint64_t lo = ld_word(blk + 2 * lane), hi = ld_word(blk + 2 * lane + 1);
         uint64_t ex = ld_word(blk + 128);
-        while (!__all(word_ok(lo, a.epoch) && word_ok(hi, a.epoch) && word_ok(ex, a.epoch))) {
+        while (!__all(word_ok(ex, a.epoch))) {
           __builtin_amdgcn_s_sleep(2);
+          ex = ld_word(blk + 128);
+        }
+        uint64_t lo = ld_word(blk + 2 * lane), hi = ld_word(blk + 2 * lane + 1);
+        while (!__all(word_ok(lo, a.epoch) && word_ok(hi, a.epoch))) {
           lo = ld_word(blk + 2 * lane);
           hi = ld_word(blk + 2 * lane + 1);
-          ex = ld_word(blk + 128);
         }
         xs[cb & 1][lane] = join_words(lo, hi);
         if (lane == 0) xe[cb & 1] = (int)(uint32_t)ex;
