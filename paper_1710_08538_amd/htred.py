@@ -138,6 +138,8 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     A, B: n x n column-major float64 GPU tensors (B upper triangular).
     Q, Z: optional preallocated outputs (allocated when None).
     workspace: optional uint8 GPU tensor of >= workspace_size(n) bytes.
+    nb: panel width 1..128; 0 takes it from the autotuner's table
+        (``autotune.py``) for the nearest order, else the library default.
     solve_solo: run every triangular solve on one workgroup (testing).
     """
     n = A.shape[0]
@@ -147,6 +149,9 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     if Z is None:
         Z = colmajor_empty(n, device=A.device)
     ldq, ldz = _ld(Q, n, "Q"), _ld(Z, n, "Z")
+    if nb == 0:
+        from paper_1710_08538_amd import autotune
+        nb = autotune.pick_nb(n)
     o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
                 n_slices=n_slices, flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
                 | (HT_FLAG_PROFILE if profile else 0)

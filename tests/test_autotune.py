@@ -1,0 +1,23 @@
+"""Host logic of the panel-width autotuner (no GPU): table lookup by the
+nearest order on a log scale, and the library default without a table."""
+import json
+
+from paper_1710_08538_amd import autotune
+
+
+def test_pick_nb_nearest_order(tmp_path):
+    path = tmp_path / "nb.json"
+    path.write_text(json.dumps({"orders": {"512": {"nb": 32}, "4096": {"nb": 128},
+                                           "1024": {"nb": 64}}}))
+    table = autotune.load_table(str(path))
+    assert table == {512: 32, 1024: 64, 4096: 128}
+    assert autotune.pick_nb(100, table) == 32
+    assert autotune.pick_nb(700, table) == 32     # log2 700 is nearer 512 than 1024
+    assert autotune.pick_nb(800, table) == 64
+    assert autotune.pick_nb(3000, table) == 128
+    assert autotune.pick_nb(16384, table) == 128
+
+
+def test_no_table_means_library_default(tmp_path):
+    assert autotune.load_table(str(tmp_path / "missing.json")) == {}
+    assert autotune.pick_nb(1000, {}) == 0
