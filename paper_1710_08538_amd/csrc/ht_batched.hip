@@ -121,24 +121,25 @@ __device__ void stage_vec(double* xs, const double* x, int k, int incx) {
   __syncthreads();
 }
 
-// Dot product of a strided global row segment with an LDS vector, sixteen
-// independent accumulators so that sixteen loads are in flight at a time
-// (the pencil workgroups are latency-bound, not bandwidth-bound).
+// Dot product of a strided global row segment with an LDS vector, NA
+// independent accumulators so that NA loads are in flight at a time (the
+// pencil workgroups are latency-bound, not bandwidth-bound).
+template <int NA = 16>
 __device__ __forceinline__ double row_dot(const double* X, size_t ldx, const double* xs, int c0,
                                           int c1) {
-  double s[16];
+  double s[NA];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) s[u] = 0.0;
+  for (int u = 0; u < NA; ++u) s[u] = 0.0;
   int c = c0;
-  for (; c + 16 <= c1; c += 16) {
+  for (; c + NA <= c1; c += NA) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) s[u] = fma(X[(size_t)(c + u) * ldx], xs[c + u], s[u]);
+    for (int u = 0; u < NA; ++u) s[u] = fma(X[(size_t)(c + u) * ldx], xs[c + u], s[u]);
   }
 #pragma unroll
-  for (int u = 0; u < 15; ++u)
+  for (int u = 0; u < NA - 1; ++u)
     if (c + u < c1) s[u] = fma(X[(size_t)(c + u) * ldx], xs[c + u], s[u]);
 #pragma unroll
-  for (int h = 8; h >= 1; h >>= 1)
+  for (int h = NA / 2; h >= 1; h >>= 1)
 #pragma unroll
     for (int u = 0; u < h; ++u) s[u] += s[u + h];
   return s[0];
@@ -351,18 +352,19 @@ __device__ __noinline__ int wg_trsv(int m, const double* B, int ldb, const doubl
   __syncthreads();
   for (int b = (m + 63) / 64 - 1; b >= 0; --b) {
     const int r0 = 64 * b, nr = min(64, m - r0);
-    {
-      // all sixteen loads of a thread are issued before the LDS stores
-      double t[64 * 64 / kBT];
 #pragma unroll
-      for (int q = 0; q < 64 * 64 / kBT; ++q) {
-        const int idx = threadIdx.x + q * kBT, rr = idx & 63, cc = idx >> 6;
+    for (int h = 0; h < 2; ++h) {
+      // eight loads of a thread in flight before their LDS stores
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = threadIdx.x + (8 * h + q) * kBT, rr = idx & 63, cc = idx >> 6;
         t[q] = (rr < nr && cc < nr && rr <= cc) ? B[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ldb]
                                                  : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < 64 * 64 / kBT; ++q) {
-        const int idx = threadIdx.x + q * kBT;
+      for (int q = 0; q < 8; ++q) {
+        const int idx = threadIdx.x + (8 * h + q) * kBT;
         dg[(idx & 63) + (idx >> 6) * kTileLd] = t[q];
       }
     }
@@ -374,6 +376,7 @@ __device__ __noinline__ int wg_trsv(int m, const double* B, int ldb, const doubl
       const double dp = (d_own != 0.0) ? d_own : 1.0;  // zero pivots only when B = 0
       const double dinv = 1.0 / dp;
       int shr = 0;
+#pragma unroll 2
       for (int rr = nr - 1; rr >= 0; --rr) {
         double t = readlane_d(rhs, rr);
         const double dr = readlane_d(dp, rr);
@@ -400,7 +403,7 @@ __device__ __noinline__ int wg_trsv(int m, const double* B, int ldb, const doubl
       if (shr) r[i] = ldexp(r[i], -kShrinkExp * shr);
     for (int i = threadIdx.x; i < r0; i += kBT) {
       const double acc = shr ? ldexp(r[i], -kShrinkExp * shr) : r[i];
-      r[i] = acc - row_dot(B + i + (size_t)r0 * ldb, ldb, r + r0, 0, nr);
+      r[i] = acc - row_dot<8>(B + i + (size_t)r0 * ldb, ldb, r + r0, 0, nr);
     }
     __syncthreads();
   }
@@ -719,9 +722,9 @@ __global__ __launch_bounds__(1024) void k_batched_order(BatchArgs a) {
   if (threadIdx.x == 0) a.counter[0] = 0;
 }
 
-// Two workgroups per CU: the helpers above are kept out of line so that
+// Three workgroups per CU: the helpers above are kept out of line so that
 // each is register-allocated on its own (no spills inside their loops).
-__global__ __launch_bounds__(kBT, 2) void k_batched(BatchArgs a) {
+__global__ __launch_bounds__(kBT, 3) void k_batched(BatchArgs a) {
   __shared__ double r[kBMax];
   __shared__ double sh[kBNW];
   __shared__ int shi[2];
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(kBT, 2) void k_batched(BatchArgs a) {
   }
 }
 
-size_t batch_grid(int batch) { return (size_t)std::max(1, std::min(batch, 2 * num_cus())); }
+size_t batch_grid(int batch) { return (size_t)std::max(1, std::min(batch, 3 * num_cus())); }
 size_t batch_stride(int nmax) {
   const size_t d = 7 * (size_t)nmax * nmax + 9 * (size_t)nmax;
   return (d * 8 + 255) / 256 * 32;  // doubles, rounded to 256 bytes
