@@ -175,3 +175,36 @@ def test_batched_graph_capture_replays():
             for M, R in zip((As[i], Bs[i], Qs[i], Zs[i]), ref[i]):
                 assert torch.equal(M, R), (rep, i)
     assert (plan.info.cpu().numpy()[:len(As)] == 0).all()
+
+
+def test_batched_full_workload():
+    """The whole batched workload in the configuration bench.py times: 2048
+    pencils, orders U{32..512} (child seeds of SeedSequence(4)), one launch.
+    Every pencil: info 0, finite output and exact zeros; every 64th pencil:
+    the invariants; four of them (largest orders among those) also parity
+    with the Moler-Stewart oracle."""
+    count = 2048
+    sizes = inputs.batch_sizes(count, 4)
+    pencils = inputs.batch_pencils(count, 4)
+    print("ht_reduce_batched full workload: %d pencils" % count, flush=True)
+    As, Bs = to_dev(pencils)
+    Qs = [htred.colmajor_empty(A.shape[0]) for A in As]
+    Zs = [htred.colmajor_empty(A.shape[0]) for A in As]
+    plan = htred.BatchedPlan(As, Bs, Qs, Zs)
+    plan.run()
+    torch.cuda.synchronize()
+    assert (plan.info.cpu().numpy()[:count] == 0).all()
+    for i in range(count):
+        H, T = As[i], Bs[i]
+        assert bool(torch.isfinite(H).all() and torch.isfinite(T).all()), i
+        assert int((torch.tril(H, -2) != 0).sum()) == 0 and int((torch.tril(T, -1) != 0).sum()) == 0
+    sample = list(range(0, count, 64))
+    for i in sample:
+        A0, B0 = pencils[i]
+        got = tuple(M.cpu().numpy() for M in (As[i], Bs[i], Qs[i], Zs[i]))
+        inv = checks.invariants(A0, B0, *got)
+        assert checks.invariants_ok(inv, int(sizes[i])), (i, inv)
+    for i in sorted(sample, key=lambda i: -int(sizes[i]))[:4]:
+        A0, B0 = pencils[i]
+        got = tuple(M.cpu().numpy() for M in (As[i], Bs[i], Qs[i], Zs[i]))
+        check_pencil(A0, B0, got, oracle.ms_ht(A0, B0)[:4])

@@ -220,3 +220,28 @@ def test_config_n4096(nb):
     ref = oracle.ms_ht(A0, B0, ncols=c)
     got = tuple(x.cpu().numpy() for x in (A, B, Q, Z))
     assert_parity(ref, got, A0, B0, upto=c)
+
+
+def test_config_n16384_illcond_full_size():
+    """The headline pencil at its full size in the configuration bench.py
+    times (n = 16384, ill-conditioned B, nb = 128): the invariants on the
+    whole output (products on the device) and sign-normalised parity of the
+    first reduced column (H(:, 0) and Q(:, 0:2), which depend on A alone) with
+    the Moler-Stewart oracle run for one column.  T and Z entries depend on a
+    numerically singular B and are judged by the invariants only."""
+    A0, B0 = inputs.workload("n16384")
+    n = A0.shape[0]
+    A = htred.to_device_colmajor(A0)
+    B = htred.to_device_colmajor(B0)
+    print("ht_reduce n=16384 illcond nb=128", flush=True)
+    Q, Z, st = htred.reduce(A, B, nb=128, stats=True)
+    torch.cuda.synchronize()
+    Ad, Bd = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    inv = checks.invariants(Ad, Bd, A, B, Q, Z)
+    assert checks.invariants_ok(inv, n), str(inv)
+    assert st["scaled_solves"] > 0 and st["columns"] == n - 2
+    del Ad, Bd
+    ref = oracle.ms_ht(A0, B0, ncols=1)[:4]
+    got = tuple(x.cpu().numpy() for x in (A, B, Q, Z))
+    d = checks.compare(ref, got, A0, B0, upto=1)
+    assert d["max_H"] <= TOL and d["max_Q"] <= TOL, d
