@@ -193,6 +193,21 @@ int ht_reduce_batched(int32_t batch, const int32_t *n_dev,
 int ht_batched_pencil_stats(const void *workspace, int32_t batch, int64_t *out, void *stream);
 
 /*
+ * ht_check -- the acceptance quantities of a reduction (Theorem A.1 and its
+ * corollary), computed on the device with the library's FP64 products:
+ *   out[0] = ||Q H Z^T - A0||_F / ||A0||_F,  out[1] = ||Q T Z^T - B0||_F / ||B0||_F,
+ *   out[2] = ||Q^T Q - I||_F,                 out[3] = ||Z^T Z - I||_F.
+ * A0, B0 (the input pencil), H, T, Q, Z: device pointers, n x n, column-major,
+ * common leading dimension ld >= max(1, n); out: host array of 4 doubles.
+ * Allocates two n x n temporaries (hipMalloc) and waits for `stream`.
+ * Returns -1..-6 for a NULL matrix (in argument order), -7 for n < 0, -8 for
+ * ld < n, -9 for a NULL out, HT_ERR_HIP if an allocation or copy fails.
+ */
+int ht_check(const double *A0, const double *B0, const double *H, const double *T,
+             const double *Q, const double *Z, int64_t n, int64_t ld, double *out,
+             void *stream);
+
+/*
  * ht_wy_gemm -- one product of the WY updates as ht_reduce computes it for
  * `prec`:  C = alpha op(A) op(B) + beta C  (op(X) = X or X^T per transA /
  * transB != 0), op(A) m x k, op(B) k x n, C m x n; device pointers,

@@ -921,6 +921,63 @@ int ht_batched_pencil_stats(const void* workspace, int32_t batch, int64_t* out, 
   return HT_OK;
 }
 
+int ht_check(const double* A0, const double* B0, const double* H, const double* T,
+             const double* Q, const double* Z, int64_t n, int64_t ld, double* out, void* stream) {
+  if (n < 0 || n > INT32_MAX) return -7;
+  if (ld < std::max<int64_t>(1, n)) return -8;
+  if (!out) return -9;
+  if (n == 0) {
+    for (int i = 0; i < 4; ++i) out[i] = 0.0;
+    return HT_OK;
+  }
+  const double* ptrs[6] = {A0, B0, H, T, Q, Z};
+  for (int i = 0; i < 6; ++i)
+    if (!ptrs[i]) return -(i + 1);
+  hipStream_t st = (hipStream_t)stream;
+  const int ni = (int)n, ldi = (int)ld;
+  const size_t sq = (size_t)ni * ni;
+  double *W1 = nullptr, *W2 = nullptr, *part = nullptr, *res = nullptr;
+  if (hipMalloc((void**)&W1, sq * 8) != hipSuccess) return HT_ERR_HIP;
+  if (hipMalloc((void**)&W2, sq * 8) != hipSuccess) { (void)hipFree(W1); return HT_ERR_HIP; }
+  if (hipMalloc((void**)&part, (size_t)2 * ni * 8 + 64 * 8) != hipSuccess) {
+    (void)hipFree(W1);
+    (void)hipFree(W2);
+    return HT_ERR_HIP;
+  }
+  res = part + 2 * (size_t)ni;
+  // res[0] = ||Q H Z^T - A0||, res[1] = ||A0||, res[2], res[3] the same for
+  // T and B0, res[4] = ||Q^T Q - I||, res[5] = ||Z^T Z - I|| (Frobenius)
+  const double* X[2] = {H, T};
+  const double* X0[2] = {A0, B0};
+  for (int t = 0; t < 2; ++t) {
+    htk::gemm(st, false, false, ni, ni, ni, 1.0, Q, ldi, X[t], ldi, 0.0, W1, ni);
+    htk::copy_mat(st, ni, ni, X0[t], ldi, W2, ni);
+    htk::gemm(st, false, true, ni, ni, ni, 1.0, W1, ni, Z, ldi, -1.0, W2, ni);
+    htk::fro_norm(st, ni, ni, W2, ni, res + 2 * t, part);
+    htk::fro_norm(st, ni, ni, X0[t], ldi, res + 2 * t + 1, part);
+  }
+  const double* O[2] = {Q, Z};
+  for (int t = 0; t < 2; ++t) {
+    htk::set_identity(st, W1, ni, ni);
+    htk::gemm(st, true, false, ni, ni, ni, 1.0, O[t], ldi, O[t], ldi, -1.0, W1, ni);
+    htk::fro_norm(st, ni, ni, W1, ni, res + 4 + t, part);
+  }
+  double h[6];
+  int rc = HT_OK;
+  if (hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    rc = HT_ERR_HIP;
+  (void)hipFree(W1);
+  (void)hipFree(W2);
+  (void)hipFree(part);
+  if (rc != HT_OK) return rc;
+  out[0] = h[0] / (h[1] > 0.0 ? h[1] : 1.0);
+  out[1] = h[2] / (h[3] > 0.0 ? h[3] : 1.0);
+  out[2] = h[4];
+  out[3] = h[5];
+  return HT_OK;
+}
+
 int ht_wy_gemm(int32_t prec, int32_t n_slices, int32_t transA, int32_t transB, int64_t m,
                int64_t n, int64_t k, double alpha, const double* A, int64_t lda, const double* B,
                int64_t ldb, double beta, double* C, int64_t ldc, void* stream) {

@@ -78,6 +78,8 @@ def lib():
         L.ht_reduce_batched.restype = ctypes.c_int
         L.ht_batched_pencil_stats.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.ht_batched_pencil_stats.restype = ctypes.c_int
+        L.ht_check.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp, vp]
+        L.ht_check.restype = ctypes.c_int
         L.ht_wy_gemm.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                  i64, i64, i64, ctypes.c_double, vp, i64, vp, i64,
                                  ctypes.c_double, vp, i64, vp]
@@ -268,6 +270,23 @@ def wy_gemm(A, B, C=None, transA=False, transB=False, alpha=1.0, beta=0.0, prec=
                             A.data_ptr(), lda, B.data_ptr(), ldb, beta, C.data_ptr(), ldc,
                             s.cuda_stream))
     return C
+
+
+def check(A0, B0, H, T, Q, Z, stream=None):
+    """Backward errors and orthogonality of a reduction, computed on the
+    device (ht_check): dict with bwd_A, bwd_B, orth_Q, orth_Z.  All six
+    matrices n x n column-major float64 GPU tensors with one leading
+    dimension."""
+    n = A0.shape[0]
+    ld = _ld(A0, n, "A0")
+    for M, name in ((B0, "B0"), (H, "H"), (T, "T"), (Q, "Q"), (Z, "Z")):
+        if _ld(M, n, name) != ld:
+            raise ValueError("all matrices must share the leading dimension")
+    out = (ctypes.c_double * 4)()
+    s = stream if stream is not None else torch.cuda.current_stream(A0.device)
+    _check(lib().ht_check(A0.data_ptr(), B0.data_ptr(), H.data_ptr(), T.data_ptr(),
+                          Q.data_ptr(), Z.data_ptr(), n, ld, out, s.cuda_stream))
+    return {"bwd_A": out[0], "bwd_B": out[1], "orth_Q": out[2], "orth_Z": out[3]}
 
 
 def workspace_size(n, nb=64):

@@ -31,7 +31,8 @@ def L():
 def test_every_declared_symbol_is_exported(L):
     names = _declared_functions()
     assert {"ht_reduce", "ht_reduce_batched", "ht_workspace_size", "ht_default_options",
-            "ht_strerror", "ht_version", "ht_batched_workspace_size"} <= set(names)
+            "ht_strerror", "ht_version", "ht_batched_workspace_size", "ht_check",
+            "ht_wy_gemm", "ht_batched_pencil_stats"} <= set(names)
     for name in names:
         assert hasattr(L, name), name
 
@@ -135,3 +136,13 @@ def htred_unsupported(L):
         if b"unsupported" in L.ht_strerror(code):
             return code
     raise AssertionError("no unsupported-option code")
+
+
+def test_check_argument_validation(L):
+    out = (ctypes.c_double * 4)()
+    z = ctypes.c_void_p(0)
+    assert L.ht_check(z, z, z, z, z, z, -1, 4, out, z) == -7
+    assert L.ht_check(z, z, z, z, z, z, 4, 3, out, z) == -8
+    assert L.ht_check(z, z, z, z, z, z, 4, 4, None, z) == -9
+    assert L.ht_check(z, z, z, z, z, z, 4, 4, out, z) == -1
+    assert L.ht_check(z, z, z, z, z, z, 0, 1, out, z) == 0 and list(out) == [0.0] * 4

@@ -245,3 +245,26 @@ def test_config_n16384_illcond_full_size():
     got = tuple(x.cpu().numpy() for x in (A, B, Q, Z))
     d = checks.compare(ref, got, A0, B0, upto=1)
     assert d["max_H"] <= TOL and d["max_Q"] <= TOL, d
+
+
+def test_ht_check_matches_host_invariants_and_sees_a_planted_error():
+    """ht_check (device products) against the host invariants on the same
+    reduction, then with one entry of H moved by delta = 1e-6 ||A||_F: Q and Z
+    are orthogonal, so ||Q (H + delta E) Z^T - A||_F grows by delta exactly
+    (up to the rounding level) and bwd_A must read about 1e-6."""
+    n = 700
+    A0, B0 = inputs.random_pencil(n, seed=77)
+    A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    print("ht_check n=%d" % n, flush=True)
+    Q, Z = htred.reduce(A, B, nb=64)
+    Ad, Bd = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    dev = htred.check(Ad, Bd, A, B, Q, Z)
+    host = checks.invariants(A0, B0, *(M.cpu().numpy() for M in (A, B, Q, Z)))
+    assert checks.invariants_ok(dict(host, **dev), n), (dev, host)
+    for key, slack in (("bwd_A", 1e-14), ("bwd_B", 1e-14), ("orth_Q", 1e-13), ("orth_Z", 1e-13)):
+        assert abs(dev[key] - host[key]) <= slack, (key, dev, host)
+    delta = 1e-6 * float(np.linalg.norm(A0))
+    A[5, 3] += delta
+    dev2 = htred.check(Ad, Bd, A, B, Q, Z)
+    assert abs(dev2["bwd_A"] - 1e-6) <= 1e-12, dev2
+    assert dev2["bwd_B"] == dev["bwd_B"] and dev2["orth_Q"] == dev["orth_Q"]
