@@ -123,7 +123,7 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
         for k in worst:
             worst[k] = max(worst[k], float(inv[k]))
     fl = float(sum(39.0 * float(n) ** 3 for n in sizes))
-    return {"pencils": count, "orders": "U{32..512}", "seed": seed,
+    return {"pencils": count, "orders": "U{32..512}", "seed": seed, "panel_width": plan.nb,
             "ms": 1000.0 * eager_s, "pencils_per_s": count / eager_s,
             "gflops_nominal": fl / eager_s / 1e9, "graph_replay_ms": 1000.0 * graph_s,
             "latency_ms_p50": float(np.percentile(lat_ms, 50)),

@@ -163,7 +163,12 @@ int ht_reduce(double *A, double *B, double *Q, double *Z, int64_t n,
  *             A, B in/out as in ht_reduce, Q and Z set (identity start);
  *   info_dev  device int32 array: 0 per success;
  *   nmax      host-side upper bound of n_dev (sizes the launch);
- *   opt       as in ht_reduce (nb, max_ir, ir_tol_factor, seed used).
+ *   opt       max_ir, ir_tol_factor and seed as in ht_reduce; nb is the panel
+ *             width of every pencil's reduction as given (1..128), and
+ *             nb = 0 (or opt NULL) runs one panel over each whole pencil.
+ *             A panel that ends before the last column is absorbed and B's
+ *             trailing block is re-triangularised by a blocked Householder
+ *             QR whose transformations go to A and Q.
  * No host synchronisation and no allocation inside: the call can be
  * captured in a hipGraph.  workspace must hold
  * ht_batched_workspace_size(batch, nmax, opt) bytes.

@@ -41,6 +41,7 @@ constexpr int kStatWords = 8;
 
 struct BatchArgs {
   int batch, nmax, max_ir;
+  int nb;               // panel width; 0: one panel over the whole pencil
   const int32_t* n;
   double* const* A;
   double* const* B;
@@ -492,36 +493,44 @@ __device__ __noinline__ bool residual(const Pencil& P, const BWork& w, int s, in
 }
 
 // Householder QR of B(c0:n, c0:n) (restores a triangular trailing block);
-// each reflector is applied to B(c:n, c+1:n), A(c:n, a0:n) and Q(:, c:n).
+// the reflectors are applied to B(c:n, c+1:n), A(c:n, a0:n) and Q(:, c:n).
+// Blocked: 32 reflectors at a time are formed on their own columns and kept
+// in compact WY form I - U S U^T (Sec. 2.4; U, S reuse the panel's storage),
+// then applied to the rest of B, to A and to Q as workgroup products.
 __device__ __noinline__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0, double* sh, Lds& ls) {
+  constexpr int NBR = 32;
   const int n = P.n, ld = P.ld;
-  for (int c = c0; c < n - 1; ++c) {
-    const int m = n - c;
-    double* col = P.B + (size_t)c + (size_t)c * ld;
-    double tau, beta;
-    wg_house(m, col, w.acol, tau, beta, true, sh);
-    if (tau == 0.0) continue;
-    // X(c:n, cols) -= tau v (v^T X)
-    auto left = [&](double* X, int ncols) {
-      for (int cc = threadIdx.x; cc < ncols; cc += kBT) {
-        double s = 0.0;
-        for (int i = 0; i < m; ++i) s = fma(w.acol[i], X[i + (size_t)cc * ld], s);
-        s *= tau;
-        for (int i = 0; i < m; ++i) X[i + (size_t)cc * ld] = fma(-s, w.acol[i], X[i + (size_t)cc * ld]);
+  for (int cb = c0; cb < n - 1; cb += NBR) {
+    const int nbr = min(NBR, n - 1 - cb);
+    const int m0 = n - cb;  // rows cb..n-1, local row index = global - cb
+    wg_zero_mat(w.U, m0, nbr, w.ld);
+    wg_zero_mat(w.S, nbr, nbr, w.ld);
+    for (int t = 0; t < nbr; ++t) {
+      const int col = cb + t, m = n - col;
+      double* u = w.U + t + (size_t)t * w.ld;
+      double tau, beta;
+      wg_house(m, P.B + (size_t)col + (size_t)col * ld, u, tau, beta, true, sh);
+      if (t > 0) wg_gemv_t(m, t, 1.0, w.U + t, w.ld, u, 0.0, w.tk, ls);
+      wg_wy_append(w.S, w.ld, t, w.tk, tau, ls);
+      // the reflector on the block's remaining columns: X -= tau u (X^T u)
+      const int nrest = cb + nbr - col - 1;
+      if (nrest > 0 && tau != 0.0) {
+        double* X = P.B + (size_t)col + (size_t)(col + 1) * ld;
+        wg_gemv_t(m, nrest, 1.0, X, ld, u, 0.0, w.tk2, ls);
+        for (int cc = 0; cc < nrest; ++cc) {
+          const double f = -tau * w.tk2[cc];
+          for (int i = threadIdx.x; i < m; i += kBT)
+            X[i + (size_t)cc * ld] = fma(f, u[i], X[i + (size_t)cc * ld]);
+        }
+        __syncthreads();
       }
-      __syncthreads();
-    };
-    left(P.B + (size_t)c + (size_t)(c + 1) * ld, n - c - 1);
-    left(P.A + (size_t)c + (size_t)a0 * ld, n - a0);
-    // Q(:, c:n) -= tau (Q v) v^T
-    for (int i = threadIdx.x; i < n; i += kBT) {
-      double s = 0.0;
-      for (int l = 0; l < m; ++l) s = fma(P.Q[i + (size_t)(c + l) * ld], w.acol[l], s);
-      s *= tau;
-      for (int l = 0; l < m; ++l)
-        P.Q[i + (size_t)(c + l) * ld] = fma(-s, w.acol[l], P.Q[i + (size_t)(c + l) * ld]);
     }
-    __syncthreads();
+    // (I - U S U^T)^T on the rest of B and on A's rows, (I - U S U^T) on Q's columns
+    if (n - (cb + nbr) > 0)
+      wg_left_wy(m0, n - (cb + nbr), nbr, P.B + (size_t)cb + (size_t)(cb + nbr) * ld, ld, w.U,
+                 w.S, w, ls);
+    wg_left_wy(m0, n - a0, nbr, P.A + (size_t)cb + (size_t)a0 * ld, ld, w.U, w.S, w, ls);
+    wg_right_wy(n, m0, nbr, P.Q + (size_t)cb * ld, ld, w.U, w.S, w, ls);
   }
 }
 
@@ -606,7 +615,7 @@ __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const 
   uint64_t panel = 0;
   while (s <= n - 3) {
     const int L = n - s - 1;
-    const int kmax = n - 2 - s;
+    const int kmax = (a.nb > 0) ? min(a.nb, n - 2 - s) : n - 2 - s;
     // zero-diagonal rule (Remark 2.2) for the trailing diagonal
     if (normB > 0.0) {
       for (int i = s + 1 + threadIdx.x; i < n; i += kBT) {
@@ -689,7 +698,9 @@ __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const 
       k = kk + 1;
     }
     tc = (int64_t)wall_clock64();
-    absorb_dense(P, w, s, k, failed, sh, ls);
+    // a panel that ends before the last column (refinement failure or the
+    // panel width) leaves B's trailing block to be re-triangularised
+    absorb_dense(P, w, s, k, failed || s + k < n - 2, sh, ls);
     tick(cnt.t_absorb);
     s += k;
     ++panel;
@@ -792,7 +803,7 @@ const int64_t* batched_stats_ptr(const void* workspace, int batch) {
 
 int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* const* A_dev,
                    double* const* B_dev, double* const* Q_dev, double* const* Z_dev,
-                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int max_ir,
+                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int nb, int max_ir,
                    double tol_factor, uint64_t seed, void* workspace) {
   if (batch <= 0) return 0;
   char* base = (char*)workspace;
@@ -800,6 +811,7 @@ int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* cons
   a.batch = batch;
   a.nmax = std::max(nmax, 1);
   a.max_ir = max_ir;
+  a.nb = nb;
   a.n = n_dev;
   a.A = A_dev;
   a.B = B_dev;

@@ -880,8 +880,11 @@ int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
       ws_bytes < batched_workspace_bytes(batch, std::max(nmax, 1)))
     return HT_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
+  // the panel width of the batched form is the caller's nb as given: 0 (or
+  // no options) means one panel over each whole pencil
+  const int nb = (opt && opt->nb > 0) ? o.nb : 0;
   batched_reduce(st, batch, n_dev, A_dev, B_dev, Q_dev, Z_dev, ld_dev, info_dev,
-                 std::max(nmax, 1), o.max_ir, o.ir_tol_factor, o.seed, workspace);
+                 std::max(nmax, 1), nb, o.max_ir, o.ir_tol_factor, o.seed, workspace);
   if (hipGetLastError() != hipSuccess) return HT_ERR_HIP;
   return HT_OK;
 }

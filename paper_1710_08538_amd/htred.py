@@ -177,7 +177,7 @@ class BatchedPlan:
     fixed list of column-major pencils (A_i, B_i, Q_i, Z_i share ld_i).  The
     arrays stay alive with the plan, so `run` may be captured in a hipGraph."""
 
-    def __init__(self, As, Bs, Qs, Zs, max_ir=10, ir_tol_factor=2.0, seed=0x5EED):
+    def __init__(self, As, Bs, Qs, Zs, max_ir=10, ir_tol_factor=2.0, seed=0x5EED, nb=None):
         dev = As[0].device if As else torch.device("cuda")
         self.batch = len(As)
         ns, lds = [], []
@@ -199,7 +199,13 @@ class BatchedPlan:
         self.pQ = torch.tensor([t.data_ptr() for t in Qs], **i64)
         self.pZ = torch.tensor([t.data_ptr() for t in Zs], **i64)
         self.info = torch.zeros(max(self.batch, 1), **i32)
-        self.opt = options(max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed)
+        # nb: panel width of every pencil's reduction (0: one panel per pencil;
+        # None: the autotuned width, see autotune.py)
+        if nb is None:
+            from paper_1710_08538_amd import autotune
+            nb = autotune.pick_batched_nb()
+        self.nb = nb
+        self.opt = options(max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, nb=nb)
         nbytes = lib().ht_batched_workspace_size(self.batch, self.nmax, ctypes.byref(self.opt))
         if nbytes == 0:
             raise HTError("invalid batched sizes (orders must be <= 512)")

@@ -21,3 +21,12 @@ def test_pick_nb_nearest_order(tmp_path):
 def test_no_table_means_library_default(tmp_path):
     assert autotune.load_table(str(tmp_path / "missing.json")) == {}
     assert autotune.pick_nb(1000, {}) == 0
+
+
+def test_batched_width_from_table(tmp_path):
+    path = tmp_path / "nb.json"
+    assert autotune.pick_batched_nb(str(path)) == autotune.BATCHED_DEFAULT
+    path.write_text(json.dumps({"orders": {}, "batched": {"nb": 32}}))
+    assert autotune.pick_batched_nb(str(path)) == 32
+    path.write_text(json.dumps({"batched": {"nb": 0}}))
+    assert autotune.pick_batched_nb(str(path)) == 0

@@ -79,6 +79,20 @@ def test_batched_pencil_stats():
                 assert 1 <= panels <= n - 2 and ir >= 0
 
 
+@pytest.mark.parametrize("nb", [16, 64])
+def test_batched_panel_widths(nb):
+    """Panels of nb columns: every panel that ends before the last column is
+    absorbed and B's trailing block is re-triangularised (blocked Householder
+    QR, 32 reflectors per block, applied to A and Q); parity with the oracle
+    for pencils of one, two and several panels."""
+    sizes = [nb - 3, nb + 5, 2 * nb + 1, 130, 200]
+    pencils = [inputs.random_pencil(n, seed=3000 + n) for n in sizes]
+    outs, info = run_batched(pencils, nb=nb)
+    assert (info == 0).all()
+    for (A0, B0), got in zip(pencils, outs):
+        check_pencil(A0, B0, got, oracle.basic_ht(A0, B0)[:4])
+
+
 def test_batched_edge_orders():
     sizes = [0, 1, 2, 3, 2, 1]
     pencils = [inputs.random_pencil(n, seed=40 + i) for i, n in enumerate(sizes)]
