@@ -124,6 +124,7 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
             worst[k] = max(worst[k], float(inv[k]))
     fl = float(sum(39.0 * float(n) ** 3 for n in sizes))
     return {"pencils": count, "orders": "U{32..512}", "seed": seed, "panel_width": plan.nb,
+            "retriangularise_block": plan.block, "workgroups_per_cu": plan.wg_per_cu,
             "ms": 1000.0 * eager_s, "pencils_per_s": count / eager_s,
             "gflops_nominal": fl / eager_s / 1e9, "graph_replay_ms": 1000.0 * graph_s,
             "latency_ms_p50": float(np.percentile(lat_ms, 50)),
@@ -132,7 +133,8 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
             "device_span_ms": float(ps[:, 1].max() / 1e6),
             "panels_total": int(ps[:, 2].sum()), "ir_steps_total": int(ps[:, 3].sum()),
             "phase_share_n_ge_480": ({k: float(ps[big, c].sum() / (ps[big, 1] - ps[big, 0]).sum())
-                                      for k, c in (("solve", 4), ("residual", 5), ("absorb", 6))}
+                                      for k, c in (("solve", 4), ("residual", 5), ("absorb", 6),
+                                                   ("retriangularise", 7))}
                                      if big.any() else None),
             "checked_sample": len(range(0, count, 32)), "invariants_ok": ok,
             "backward_error_max": worst}

@@ -83,6 +83,12 @@ typedef struct {
                                 default 2.0 (Sec. 2.3) */
     uint64_t seed;           /* stream for the zero-diagonal perturbation rho
                                 (Sec. 3.2.1) */
+    int32_t batch_block;     /* ht_reduce_batched: reflectors per block of the
+                                Householder QR that re-triangularises B after a
+                                panel; 0 = default 32.  Must be 1..64. */
+    int32_t batch_wg_per_cu; /* ht_reduce_batched: resident workgroups per
+                                compute unit (each reduces one pencil at a
+                                time); 0 = default 3.  Must be 1..3. */
 } ht_options;
 
 /* flags */
@@ -190,8 +196,8 @@ int ht_reduce_batched(int32_t batch, const int32_t *n_dev,
  *   2     number of panels (absorptions) of its reduction;
  *   3     number of iterative-refinement steps (Sec. 3.2.2);
  *   4, 5, 6  nanoseconds spent in the factored solves, in the residuals and
- *         in the absorptions;
- *   7     reserved (0).
+ *         in the absorptions (the two-sided panel updates);
+ *   7     nanoseconds spent re-triangularising B after a panel.
  * Returns -1 for a NULL workspace, -2 for batch < 0, -3 for a NULL out,
  * HT_ERR_HIP if the copy fails.  Meaningless before the batched call ran.
  */

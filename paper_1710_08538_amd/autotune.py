@@ -9,10 +9,13 @@ generator), keeps the fastest nb per order, and writes the table to
 from the table entry of the nearest order (log scale); without a table it
 uses the library default.
 
-With ``--batched`` it also times the batched form on the batched workload
-(orders U{32..512}, child seeds of SeedSequence(4)) for panel widths 0 (one
-panel per pencil), 32, 64 and 128, and stores the fastest; ``BatchedPlan``
-uses it when no nb is given.
+With ``--batched`` it also tunes the batched form on the batched workload
+(orders U{32..512}, child seeds of SeedSequence(4)): the panel width (0, one
+panel per pencil, or 32, 64, 128), the block width of the Householder QR
+that re-triangularises B after each panel (16, 32, 64 reflectors) and the
+launch shape (2 or 3 resident workgroups per compute unit).  It times every
+combination, stores the fastest, and ``BatchedPlan`` uses it for whatever
+the caller leaves unset.
 
     python -m paper_1710_08538_amd.autotune [--orders 1024 2048 4096] [--nb 32 64 128] [--batched]
 """
@@ -36,22 +39,27 @@ def load_table(path=TABLE):
         return {}
 
 
-BATCHED_DEFAULT = 64
-BATCHED_CANDIDATES = (0, 32, 64, 128)
+BATCHED_DEFAULT = {"nb": 64, "block": 32, "wg_per_cu": 3}
+BATCHED_CANDIDATES = ([(0, 32, 3)] +
+                      [(nb, blk, wpc) for nb in (32, 64, 128) for blk in (16, 32, 64)
+                       for wpc in (2, 3)])
 
 
 def load_batched(path=TABLE):
-    """The tuned panel width of the batched form, or None."""
+    """The tuned parameters of the batched form, or None."""
     try:
         with open(path) as f:
-            return int(json.load(f)["batched"]["nb"])
+            ent = json.load(f)["batched"]
+        return {k: int(ent[k]) for k in BATCHED_DEFAULT}
     except (OSError, ValueError, KeyError, TypeError):
         return None
 
 
-def pick_batched_nb(path=TABLE):
-    nb = load_batched(path)
-    return BATCHED_DEFAULT if nb is None else nb
+def pick_batched(path=TABLE):
+    """{"nb", "block", "wg_per_cu"} for the batched form: the tuned values,
+    else the defaults."""
+    got = load_batched(path)
+    return dict(BATCHED_DEFAULT) if got is None else got
 
 
 def pick_nb(n, table=None):
@@ -82,18 +90,19 @@ def time_reduce(htred, inputs, torch, n, nb, reps):
     return best
 
 
-def time_batched(htred, inputs, torch, nb, count=2048, seed=4, reps=1):
-    pencils = inputs.batch_pencils(count, seed)
-    A0s = [htred.to_device_colmajor(A) for A, _ in pencils]
-    B0s = [htred.to_device_colmajor(B) for _, B in pencils]
-    As = [A.clone() for A in A0s]
-    Bs = [B.clone() for B in B0s]
-    Qs = [htred.colmajor_empty(A.shape[0]) for A in As]
-    Zs = [htred.colmajor_empty(A.shape[0]) for A in As]
-    plan = htred.BatchedPlan(As, Bs, Qs, Zs, nb=nb)
+def batched_key(nb, block, wpc):
+    return "nb=%d,block=%d,wg_per_cu=%d" % (nb, block, wpc)
+
+
+def time_batched(htred, torch, mats, cand, reps=1):
+    """Best of `reps` timed runs (after one warm-up) of the batched form with
+    parameters cand = (nb, block, wg_per_cu) on the pencils `mats`."""
+    A0s, B0s, As, Bs, Qs, Zs = mats
+    nb, block, wpc = cand
+    plan = htred.BatchedPlan(As, Bs, Qs, Zs, nb=nb, block=block, wg_per_cu=wpc)
     best = float("inf")
     for r in range(reps + 1):
-        for i in range(count):
+        for i in range(len(As)):
             As[i].copy_(A0s[i])
             Bs[i].copy_(B0s[i])
         torch.cuda.synchronize()
@@ -102,28 +111,36 @@ def time_batched(htred, inputs, torch, nb, count=2048, seed=4, reps=1):
         torch.cuda.synchronize()
         if r > 0:
             best = min(best, time.time() - t)
-    if not bool((plan.info[:count].cpu() == 0).all()):
-        raise RuntimeError("batched reduction reported errors at nb=%d" % nb)
+    if not bool((plan.info[:len(As)].cpu() == 0).all()):
+        raise RuntimeError("batched reduction reported errors at %s" % batched_key(*cand))
     return best
 
 
-def tune_batched(candidates=BATCHED_CANDIDATES, reps=1, path=TABLE):
+def tune_batched(candidates=BATCHED_CANDIDATES, reps=1, path=TABLE, count=2048, seed=4):
     import torch
     from paper_1710_08538_amd import htred, inputs
     if not torch.cuda.is_available():
         raise RuntimeError("the autotuner times the GPU path and needs a GPU")
+    pencils = inputs.batch_pencils(count, seed)
+    A0s = [htred.to_device_colmajor(A) for A, _ in pencils]
+    B0s = [htred.to_device_colmajor(B) for _, B in pencils]
+    mats = (A0s, B0s, [A.clone() for A in A0s], [B.clone() for B in B0s],
+            [htred.colmajor_empty(A.shape[0]) for A in A0s],
+            [htred.colmajor_empty(A.shape[0]) for A in A0s])
     times = {}
-    for nb in candidates:
-        times[nb] = time_batched(htred, inputs, torch, nb, reps=reps)
-        print("autotune: batched nb=%d %.3f s" % (nb, times[nb]), flush=True)
+    for cand in candidates:
+        times[cand] = time_batched(htred, torch, mats, cand, reps=reps)
+        print("autotune: batched %s %.3f s" % (batched_key(*cand), times[cand]), flush=True)
+        torch.cuda.empty_cache()
     best = min(times, key=times.get)
     try:
         with open(path) as f:
             data = json.load(f)
     except (OSError, ValueError):
         data = {}
-    data["batched"] = {"nb": best, "workload": "2048 pencils, orders U{32..512}, seed 4",
-                       "seconds": {str(k): v for k, v in times.items()}}
+    data["batched"] = {"nb": best[0], "block": best[1], "wg_per_cu": best[2],
+                       "workload": "%d pencils, orders U{32..512}, seed %d" % (count, seed),
+                       "seconds": {batched_key(*k): v for k, v in times.items()}}
     with open(path, "w") as f:
         json.dump(data, f, indent=1)
     return data

@@ -32,6 +32,14 @@
 
 namespace htk {
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64: lane l = 16 g + c supplies a = A(c, g) and
+// b = B(g, c) and holds D(g + 4 e, c) in register e
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
 namespace {
 
 constexpr int kBT = 256;  // threads per pencil workgroup
@@ -42,6 +50,7 @@ constexpr int kStatWords = 8;
 struct BatchArgs {
   int batch, nmax, max_ir;
   int nb;               // panel width; 0: one panel over the whole pencil
+  int rblock;           // reflectors per block of B's re-triangularisation
   const int32_t* n;
   double* const* A;
   double* const* B;
@@ -285,51 +294,81 @@ __device__ __noinline__ void wg_house(int m, double* x, double* v, double& tau, 
 }
 
 // C(0:m, 0:n) = alpha op(A) op(B) + beta C (C distinct from A, B).
-//   op(A): m x k (A or A^T),  op(B): k x n (B or B^T); k <= kBMax.
-// Eight columns of op(B) at a time are staged in LDS; each thread forms
-// eight outputs of a row with every A entry it loads, four loads in flight.
+//   op(A): m x k (A or A^T),  op(B): k x n (B or B^T).
+// FP64 matrix cores, fragments loaded straight from global memory: each
+// wavefront owns 32 x 32 tiles of C and forms their transposes,
+//   C^T tile (16 x 16) += op(B)^T fragment (16 x 4) . op(A)^T fragment (4 x 16),
+// so that in the accumulator lane 16 g + c holds C(i0 + c, j0 + g + 4 q) in
+// register q: the epilogue writes 16 consecutive rows of a column per lane
+// group.  Lane (g, c) loads op(A)(i0 + c, l) and op(B)(l, j0 + c) for
+// l = l0 + 4 u + g; entries past m, n or k count as zero (their loads are
+// clamped to row / column 0 and index k - 1, all in bounds).
 __device__ __noinline__ void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
-                        int lda, const double* B, int ldb, double beta, double* C, int ldc,
-                        Lds& ls) {
-  constexpr int NC = 8;
-  for (int c0 = 0; c0 < n; c0 += NC) {
-    const int nc = min(NC, n - c0);
-    for (int idx = threadIdx.x; idx < NC * k; idx += kBT) {
-      const int l = idx % k, cc = idx / k;
-      ls.bs[idx] = (cc < nc) ? (tb ? B[(c0 + cc) + (size_t)l * ldb] : B[l + (size_t)(c0 + cc) * ldb])
-                            : 0.0;
+                        int lda, const double* B, int ldb, double beta, double* C, int ldc) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int tm = (m + 31) / 32, tn = (n + 31) / 32;
+  // op(A)(i, l) = A[i * sai + l * sal],  op(B)(l, j) = B[l * sbl + j * sbj]
+  const size_t sai = ta ? (size_t)lda : 1, sal = ta ? 1 : (size_t)lda;
+  const size_t sbl = tb ? (size_t)ldb : 1, sbj = tb ? 1 : (size_t)ldb;
+  for (int t = wv; t < tm * tn; t += kBT / 64) {
+    const int i0 = 32 * (t % tm), j0 = 32 * (t / tm);
+    bool ra[2], rb[2];
+    const double* pa[2];
+    const double* pb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = i0 + 16 * h + c, j = j0 + 16 * h + c;
+      ra[h] = i < m;
+      rb[h] = j < n;
+      pa[h] = A + (ra[h] ? (size_t)i * sai : 0);
+      pb[h] = B + (rb[h] ? (size_t)j * sbj : 0);
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < m; i += kBT) {
-      double sv[NC];
+    v4d acc[2][2];
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc) sv[cc] = 0.0;
-      const double* a = ta ? A + (size_t)i * lda : A + i;
-      const size_t as = ta ? 1 : (size_t)lda;
-      int l = 0;
-      for (; l + 4 <= k; l += 4) {
-        double av[4];
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) av[u] = a[(size_t)(l + u) * as];
+      for (int q = 0; q < 2; ++q) acc[r][q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < k; l0 += 16) {
+      double av[4][2], bv[4][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u) {
+        // loads from a clamped (in-bounds) index, then a select: no branches
+        const int l = l0 + 4 * u + g;
+        const bool lk = l < k;
+        const size_t lc = (size_t)min(l, k - 1);
 #pragma unroll
-          for (int cc = 0; cc < NC; ++cc) sv[cc] = fma(av[u], ls.bs[cc * k + l + u], sv[cc]);
-      }
-      for (; l < k; ++l) {
-        const double av = a[(size_t)l * as];
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) sv[cc] = fma(av, ls.bs[cc * k + l], sv[cc]);
+        for (int h = 0; h < 2; ++h) {
+          const double x = pa[h][lc * sal], y = pb[h][lc * sbl];
+          av[u][h] = (lk && ra[h]) ? x : 0.0;
+          bv[u][h] = (lk && rb[h]) ? y : 0.0;
+        }
       }
 #pragma unroll
-      for (int cc = 0; cc < NC; ++cc)
-        if (cc < nc) {
-          double* p = C + i + (size_t)(c0 + cc) * ldc;
-          *p = (beta == 0.0) ? alpha * sv[cc] : fma(alpha, sv[cc], beta * *p);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) acc[r][q] = mfma4(bv[u][q], av[u][r], acc[r][q]);
+    }
+    // acc[r][q] register e: C(i0 + 16 r + c, j0 + 16 q + g + 4 e)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int i = i0 + 16 * r + c;
+      if (i >= m) continue;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = j0 + 16 * q + g + 4 * e;
+          if (j < n) {
+            double* p = C + i + (size_t)j * ldc;
+            *p = (beta == 0.0) ? alpha * acc[r][q][e] : fma(alpha, acc[r][q][e], beta * *p);
+          }
         }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // y = B(0:m, 0:m) x for upper triangular B (zeros below the diagonal, read
@@ -418,17 +457,17 @@ __device__ __noinline__ int wg_trsv(int m, const double* B, int ldb, const doubl
 __device__ __noinline__ void wg_right_wy(int rows, int L, int k, double* X, int ldx, const double* V,
                             const double* T, const BWork& w, Lds& ls) {
   if (rows <= 0 || k <= 0) return;
-  wg_gemm(false, false, rows, k, L, 1.0, X, ldx, V, w.ld, 0.0, w.P, w.ld, ls);
-  wg_gemm(false, false, rows, k, k, 1.0, w.P, w.ld, T, w.ld, 0.0, w.P2, w.ld, ls);
-  wg_gemm(false, true, rows, L, k, -1.0, w.P2, w.ld, V, w.ld, 1.0, X, ldx, ls);
+  wg_gemm(false, false, rows, k, L, 1.0, X, ldx, V, w.ld, 0.0, w.P, w.ld);
+  wg_gemm(false, false, rows, k, k, 1.0, w.P, w.ld, T, w.ld, 0.0, w.P2, w.ld);
+  wg_gemm(false, true, rows, L, k, -1.0, w.P2, w.ld, V, w.ld, 1.0, X, ldx);
 }
 // X(0:L, cols) -= U S^T (U^T X): X is L x ncols
 __device__ __noinline__ void wg_left_wy(int L, int ncols, int k, double* X, int ldx, const double* U,
                            const double* S, const BWork& w, Lds& ls) {
   if (ncols <= 0 || k <= 0) return;
-  wg_gemm(true, false, k, ncols, L, 1.0, U, w.ld, X, ldx, 0.0, w.P, w.ld, ls);
-  wg_gemm(true, false, k, ncols, k, 1.0, S, w.ld, w.P, w.ld, 0.0, w.P2, w.ld, ls);
-  wg_gemm(false, false, L, ncols, k, -1.0, U, w.ld, w.P2, w.ld, 1.0, X, ldx, ls);
+  wg_gemm(true, false, k, ncols, L, 1.0, U, w.ld, X, ldx, 0.0, w.P, w.ld);
+  wg_gemm(true, false, k, ncols, k, 1.0, S, w.ld, w.P, w.ld, 0.0, w.P2, w.ld);
+  wg_gemm(false, false, L, ncols, k, -1.0, U, w.ld, w.P2, w.ld, 1.0, X, ldx);
 }
 
 struct Pencil {
@@ -494,14 +533,15 @@ __device__ __noinline__ bool residual(const Pencil& P, const BWork& w, int s, in
 
 // Householder QR of B(c0:n, c0:n) (restores a triangular trailing block);
 // the reflectors are applied to B(c:n, c+1:n), A(c:n, a0:n) and Q(:, c:n).
-// Blocked: 32 reflectors at a time are formed on their own columns and kept
-// in compact WY form I - U S U^T (Sec. 2.4; U, S reuse the panel's storage),
-// then applied to the rest of B, to A and to Q as workgroup products.
-__device__ __noinline__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0, double* sh, Lds& ls) {
-  constexpr int NBR = 32;
+// Blocked: rb (1..64) reflectors at a time are formed on their own columns
+// and kept in compact WY form I - U S U^T (Sec. 2.4; U, S reuse the panel's
+// storage), then applied to the rest of B, to A and to Q as workgroup
+// products.
+__device__ __noinline__ void retriangularise(const Pencil& P, const BWork& w, int c0, int a0, int rb,
+                                             double* sh, Lds& ls) {
   const int n = P.n, ld = P.ld;
-  for (int cb = c0; cb < n - 1; cb += NBR) {
-    const int nbr = min(NBR, n - 1 - cb);
+  for (int cb = c0; cb < n - 1; cb += rb) {
+    const int nbr = min(rb, n - 1 - cb);
     const int m0 = n - cb;  // rows cb..n-1, local row index = global - cb
     wg_zero_mat(w.U, m0, nbr, w.ld);
     wg_zero_mat(w.S, nbr, nbr, w.ld);
@@ -538,14 +578,14 @@ __device__ __noinline__ void retriangularise(const Pencil& P, const BWork& w, in
 // s..j-1 (j = s+k) are reduced, columns j..n-1 still carry the pending
 // updates.  failed: the panel ended at column j by a refinement failure.
 __device__ __noinline__ void absorb_dense(const Pencil& P, const BWork& w, int s, int k, bool failed,
-                             double* sh, Lds& ls) {
+                             Lds& ls) {
   const int n = P.n, ld = P.ld, L = n - s - 1, j = s + k;
   if (k > 0) {
     // A: rows 0..s take the right transformation on columns s+1..n-1; rows
     // s+1.. of the unreduced columns j..n-1 take the column update (a)
     wg_right_wy(s + 1, L, k, P.A + (size_t)(s + 1) * ld, ld, w.V, w.T, w, ls);
     double* Aj = P.A + (size_t)(s + 1) + (size_t)j * ld;
-    wg_gemm(false, true, L, n - j, k, -1.0, w.Y, w.ld, w.V + (j - s - 1), w.ld, 1.0, Aj, ld, ls);
+    wg_gemm(false, true, L, n - j, k, -1.0, w.Y, w.ld, w.V + (j - s - 1), w.ld, 1.0, Aj, ld);
     wg_left_wy(L, n - j, k, Aj, ld, w.U, w.S, w, ls);
     // B: (I - U S^T U^T) B (I - V T V^T) on rows/columns s+1..n-1 (rows
     // 0..s only from the right)
@@ -554,9 +594,9 @@ __device__ __noinline__ void absorb_dense(const Pencil& P, const BWork& w, int s
     // Q <- Q (I - U S U^T), Z <- Z (I - V T V^T) on columns s+1..n-1
     {
       double* X = P.Q + (size_t)(s + 1) * ld;
-      wg_gemm(false, false, n, k, L, 1.0, X, ld, w.U, w.ld, 0.0, w.P, w.ld, ls);
-      wg_gemm(false, false, n, k, k, 1.0, w.P, w.ld, w.S, w.ld, 0.0, w.P2, w.ld, ls);
-      wg_gemm(false, true, n, L, k, -1.0, w.P2, w.ld, w.U, w.ld, 1.0, X, ld, ls);
+      wg_gemm(false, false, n, k, L, 1.0, X, ld, w.U, w.ld, 0.0, w.P, w.ld);
+      wg_gemm(false, false, n, k, k, 1.0, w.P, w.ld, w.S, w.ld, 0.0, w.P2, w.ld);
+      wg_gemm(false, true, n, L, k, -1.0, w.P2, w.ld, w.U, w.ld, 1.0, X, ld);
     }
     wg_right_wy(n, L, k, P.Z + (size_t)(s + 1) * ld, ld, w.V, w.T, w, ls);
   }
@@ -566,15 +606,15 @@ __device__ __noinline__ void absorb_dense(const Pencil& P, const BWork& w, int s
   for (int c = s + 1; c <= clast && c < n; ++c)
     for (int i = c + 1 + threadIdx.x; i < n; i += kBT) P.B[i + (size_t)c * ld] = 0.0;
   __syncthreads();
-  if (failed) retriangularise(P, w, j + 1, j, sh, ls);
 }
 
 // Counters of one pencil's reduction: panels (absorptions), refinement
-// steps, and device-clock ticks spent in the solves, the residuals and the
-// absorptions (read by thread 0 between the helpers' closing barriers).
+// steps, and device-clock ticks spent in the solves, the residuals, the
+// absorptions and the re-triangularisations of B (read by thread 0 between
+// the helpers' closing barriers).
 struct PencilCount {
   int panels, ir;
-  int64_t t_solve, t_resid, t_absorb;
+  int64_t t_solve, t_resid, t_absorb, t_retri;
 };
 
 __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const BWork& w, uint64_t seed,
@@ -602,7 +642,7 @@ __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const 
     }
   bss = block_sum(bss, sh);
   const double normB = sqrt(bss) / bsc;
-  PencilCount cnt = {0, 0, 0, 0, 0};
+  PencilCount cnt = {0, 0, 0, 0, 0, 0};
   if (n <= 2) return cnt;
   int64_t tc = 0;
   auto tick = [&](int64_t& acc) {
@@ -700,8 +740,13 @@ __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const 
     tc = (int64_t)wall_clock64();
     // a panel that ends before the last column (refinement failure or the
     // panel width) leaves B's trailing block to be re-triangularised
-    absorb_dense(P, w, s, k, failed || s + k < n - 2, sh, ls);
+    const bool retri = failed || s + k < n - 2;
+    absorb_dense(P, w, s, k, retri, ls);
     tick(cnt.t_absorb);
+    if (retri) {
+      retriangularise(P, w, s + k + 1, s + k, a.rblock, sh, ls);
+      tick(cnt.t_retri);
+    }
     s += k;
     ++panel;
   }
@@ -758,7 +803,7 @@ __global__ __launch_bounds__(kBT, 3) void k_batched(BatchArgs a) {
     P.Z = a.Z[pi];
     const int64_t t0 = (int64_t)wall_clock64();
     int info = 0;
-    PencilCount cnt = {0, 0, 0, 0, 0};
+    PencilCount cnt = {0, 0, 0, 0, 0, 0};
     if (P.n < 0 || P.n > a.nmax || P.ld < max(1, P.n) ||
         (P.n > 0 && (!P.A || !P.B || !P.Q || !P.Z)))
       info = -1;
@@ -775,13 +820,17 @@ __global__ __launch_bounds__(kBT, 3) void k_batched(BatchArgs a) {
       st[4] = cnt.t_solve;
       st[5] = cnt.t_resid;
       st[6] = cnt.t_absorb;
-      st[7] = 0;
+      st[7] = cnt.t_retri;
     }
     __syncthreads();
   }
 }
 
-size_t batch_grid(int batch) { return (size_t)std::max(1, std::min(batch, 3 * num_cus())); }
+// resident workgroups: wg_per_cu (<= 3, the occupancy k_batched is built
+// for) per compute unit, no more than there are pencils
+size_t batch_grid(int batch, int wg_per_cu) {
+  return (size_t)std::max(1, std::min(batch, wg_per_cu * num_cus()));
+}
 size_t batch_stride(int nmax) {
   const size_t d = 7 * (size_t)nmax * nmax + 9 * (size_t)nmax;
   return (d * 8 + 255) / 256 * 32;  // doubles, rounded to 256 bytes
@@ -792,9 +841,10 @@ size_t stats_bytes(int batch) { return ((size_t)batch * kStatWords * 8 + 255) / 
 
 }  // namespace
 
-size_t batched_workspace_bytes(int batch, int nmax) {
+size_t batched_workspace_bytes(int batch, int nmax, int wg_per_cu) {
   if (batch <= 0) return 256;
-  return 256 + order_bytes(batch) + stats_bytes(batch) + batch_grid(batch) * batch_stride(nmax) * 8;
+  return 256 + order_bytes(batch) + stats_bytes(batch) +
+         batch_grid(batch, wg_per_cu) * batch_stride(nmax) * 8;
 }
 
 const int64_t* batched_stats_ptr(const void* workspace, int batch) {
@@ -803,8 +853,8 @@ const int64_t* batched_stats_ptr(const void* workspace, int batch) {
 
 int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* const* A_dev,
                    double* const* B_dev, double* const* Q_dev, double* const* Z_dev,
-                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int nb, int max_ir,
-                   double tol_factor, uint64_t seed, void* workspace) {
+                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int nb, int rblock,
+                   int wg_per_cu, int max_ir, double tol_factor, uint64_t seed, void* workspace) {
   if (batch <= 0) return 0;
   char* base = (char*)workspace;
   BatchArgs a;
@@ -812,6 +862,7 @@ int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* cons
   a.nmax = std::max(nmax, 1);
   a.max_ir = max_ir;
   a.nb = nb;
+  a.rblock = std::min(std::max(rblock, 1), 64);
   a.n = n_dev;
   a.A = A_dev;
   a.B = B_dev;
@@ -827,7 +878,8 @@ int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* cons
   a.tol_factor = tol_factor;
   a.seed = seed;
   hipLaunchKernelGGL(k_batched_order, dim3(1), dim3(1024), 0, st, a);
-  hipLaunchKernelGGL(k_batched, dim3((unsigned)batch_grid(batch)), dim3(kBT), 0, st, a);
+  const int wpc = std::min(std::max(wg_per_cu, 1), 3);
+  hipLaunchKernelGGL(k_batched, dim3((unsigned)batch_grid(batch, wpc)), dim3(kBT), 0, st, a);
   return 0;
 }
 

@@ -716,6 +716,8 @@ int ht_default_options(ht_options* opt) {
   opt->flags = 0;
   opt->ir_tol_factor = 2.0;
   opt->seed = 0x5EEDull;
+  opt->batch_block = 32;
+  opt->batch_wg_per_cu = 3;
   return 0;
 }
 
@@ -729,6 +731,10 @@ static int resolve_opts(const ht_options* in, ht_options* out) {
   if (out->max_ir < 0) return -10;
   if (out->qmode < 0 || out->qmode > 2 || out->zmode < 0 || out->zmode > 2) return -10;
   if (!(out->ir_tol_factor >= 0.0)) return -10;
+  if (out->batch_block == 0) out->batch_block = 32;
+  if (out->batch_wg_per_cu == 0) out->batch_wg_per_cu = 3;
+  if (out->batch_block < 1 || out->batch_block > 64) return -10;
+  if (out->batch_wg_per_cu < 1 || out->batch_wg_per_cu > 3) return -10;
   if (out->prec < HT_PREC_FP64 || out->prec > HT_PREC_SPLIT_FP8) return -10;
   if (out->prec != HT_PREC_FP64) {
     const int fmt = out->prec == HT_PREC_SPLIT_BF16 ? 0 : 1;
@@ -857,7 +863,7 @@ const char* ht_version(void) { return "htred 0.1 gfx950"; }
 size_t ht_batched_workspace_size(int32_t batch, int32_t nmax, const ht_options* opt) {
   ht_options o;
   if (resolve_opts(opt, &o) != 0 || batch < 0 || nmax < 0 || nmax > 512) return 0;
-  return batched_workspace_bytes(batch, std::max(nmax, 1)) + 256;
+  return batched_workspace_bytes(batch, std::max(nmax, 1), o.batch_wg_per_cu) + 256;
 }
 
 int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
@@ -877,14 +883,15 @@ int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
   if (rc != 0) return rc;
   if (o.prec != HT_PREC_FP64) return HT_ERR_UNSUPPORTED;
   if (!workspace || ((uintptr_t)workspace & 255) ||
-      ws_bytes < batched_workspace_bytes(batch, std::max(nmax, 1)))
+      ws_bytes < batched_workspace_bytes(batch, std::max(nmax, 1), o.batch_wg_per_cu))
     return HT_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   // the panel width of the batched form is the caller's nb as given: 0 (or
   // no options) means one panel over each whole pencil
   const int nb = (opt && opt->nb > 0) ? o.nb : 0;
   batched_reduce(st, batch, n_dev, A_dev, B_dev, Q_dev, Z_dev, ld_dev, info_dev,
-                 std::max(nmax, 1), nb, o.max_ir, o.ir_tol_factor, o.seed, workspace);
+                 std::max(nmax, 1), nb, o.batch_block, o.batch_wg_per_cu, o.max_ir,
+                 o.ir_tol_factor, o.seed, workspace);
   if (hipGetLastError() != hipSuccess) return HT_ERR_HIP;
   return HT_OK;
 }
@@ -919,7 +926,7 @@ int ht_batched_pencil_stats(const void* workspace, int32_t batch, int64_t* out, 
     o[4] = ns(r[4]);
     o[5] = ns(r[5]);
     o[6] = ns(r[6]);
-    o[7] = 0;
+    o[7] = ns(r[7]);
   }
   return HT_OK;
 }

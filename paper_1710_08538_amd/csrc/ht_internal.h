@@ -129,11 +129,12 @@ int num_cus();
 
 // Batched form: workspace bytes and the two launches (pencils of order
 // <= nmax <= 512, one workgroup per pencil).
-size_t batched_workspace_bytes(int batch, int nmax);
+size_t batched_workspace_bytes(int batch, int nmax, int wg_per_cu);
 const int64_t* batched_stats_ptr(const void* workspace, int batch);
 int batched_reduce(hipStream_t st, int batch, const int32_t* n_dev, double* const* A_dev,
                    double* const* B_dev, double* const* Q_dev, double* const* Z_dev,
-                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int nb, int max_ir,
+                   const int32_t* ld_dev, int32_t* info_dev, int nmax, int nb, int rblock,
+                   int wg_per_cu, int max_ir,
                    double tol_factor, uint64_t seed, void* workspace);
 
 }  // namespace htk

@@ -27,7 +27,8 @@ class Options(ctypes.Structure):
                 ("max_ir", ctypes.c_int32), ("qmode", ctypes.c_int32),
                 ("zmode", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("ir_tol_factor", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("ir_tol_factor", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("batch_block", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -177,7 +178,8 @@ class BatchedPlan:
     fixed list of column-major pencils (A_i, B_i, Q_i, Z_i share ld_i).  The
     arrays stay alive with the plan, so `run` may be captured in a hipGraph."""
 
-    def __init__(self, As, Bs, Qs, Zs, max_ir=10, ir_tol_factor=2.0, seed=0x5EED, nb=None):
+    def __init__(self, As, Bs, Qs, Zs, max_ir=10, ir_tol_factor=2.0, seed=0x5EED, nb=None,
+                 block=None, wg_per_cu=None):
         dev = As[0].device if As else torch.device("cuda")
         self.batch = len(As)
         ns, lds = [], []
@@ -199,16 +201,20 @@ class BatchedPlan:
         self.pQ = torch.tensor([t.data_ptr() for t in Qs], **i64)
         self.pZ = torch.tensor([t.data_ptr() for t in Zs], **i64)
         self.info = torch.zeros(max(self.batch, 1), **i32)
-        # nb: panel width of every pencil's reduction (0: one panel per pencil;
-        # None: the autotuned width, see autotune.py)
-        if nb is None:
-            from paper_1710_08538_amd import autotune
-            nb = autotune.pick_batched_nb()
-        self.nb = nb
-        self.opt = options(max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, nb=nb)
+        # nb: panel width of every pencil's reduction (0: one panel per pencil);
+        # block: reflectors per block of B's re-triangularisation; wg_per_cu:
+        # resident workgroups per compute unit.  None: the autotuned value
+        # (autotune.py), else the library default.
+        from paper_1710_08538_amd import autotune
+        tuned = autotune.pick_batched()
+        self.nb = tuned["nb"] if nb is None else nb
+        self.block = tuned["block"] if block is None else block
+        self.wg_per_cu = tuned["wg_per_cu"] if wg_per_cu is None else wg_per_cu
+        self.opt = options(max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, nb=self.nb,
+                           batch_block=self.block, batch_wg_per_cu=self.wg_per_cu)
         nbytes = lib().ht_batched_workspace_size(self.batch, self.nmax, ctypes.byref(self.opt))
         if nbytes == 0:
-            raise HTError("invalid batched sizes (orders must be <= 512)")
+            raise HTError("invalid batched sizes or options (orders must be <= 512)")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.keep = (As, Bs, Qs, Zs)
 
@@ -224,7 +230,7 @@ class BatchedPlan:
     def pencil_stats(self, stream=None):
         """Per-pencil record of the last run as a host int64 tensor of shape
         (batch, 8): start_ns, end_ns, panels, ir_steps, solve_ns, residual_ns,
-        absorb_ns, 0.  Waits for the stream."""
+        absorb_ns, retriangularise_ns.  Waits for the stream."""
         s = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
         out = torch.zeros((max(self.batch, 1), 8), dtype=torch.int64)
         _check(lib().ht_batched_pencil_stats(self.ws.data_ptr(), self.batch, out.data_ptr(),

@@ -43,6 +43,7 @@ def test_defaults_and_struct_size(L):
     assert L.ht_default_options(ctypes.byref(o)) == 0
     assert o.struct_size == ctypes.sizeof(htred.Options)
     assert o.nb == 64 and o.max_ir == 10 and o.ir_tol_factor == 2.0
+    assert o.batch_block == 32 and o.batch_wg_per_cu == 3
 
 
 def test_workspace_size_grows_with_n(L):
@@ -87,6 +88,20 @@ def test_batched_argument_validation(L):
                                ctypes.byref(o), None, 0, None) == 0
     assert L.ht_reduce_batched(3, None, None, None, None, None, None, None, 64,
                                ctypes.byref(o), None, 0, None) == -2
+    # batched shape options: 0 = default, out of range rejected; the
+    # workspace holds one scratch area per resident workgroup
+    for kw in ({"batch_block": 65}, {"batch_block": -1}, {"batch_wg_per_cu": 4},
+               {"batch_wg_per_cu": -1}):
+        assert L.ht_batched_workspace_size(4, 64, ctypes.byref(htred.options(**kw))) == 0, kw
+    zero = htred.options(batch_block=0, batch_wg_per_cu=0)
+    assert L.ht_batched_workspace_size(4, 64, ctypes.byref(zero)) == \
+        L.ht_batched_workspace_size(4, 64, ctypes.byref(o))
+    big = [L.ht_batched_workspace_size(4096, 512, ctypes.byref(htred.options(batch_wg_per_cu=w)))
+           for w in (1, 2, 3)]
+    assert 0 < big[0] < big[1] < big[2]
+    few = [L.ht_batched_workspace_size(3, 512, ctypes.byref(htred.options(batch_wg_per_cu=w)))
+           for w in (1, 3)]
+    assert few[0] == few[1]  # never more workgroups than pencils
 
 
 def test_wy_gemm_argument_validation(L):

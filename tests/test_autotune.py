@@ -23,10 +23,21 @@ def test_no_table_means_library_default(tmp_path):
     assert autotune.pick_nb(1000, {}) == 0
 
 
-def test_batched_width_from_table(tmp_path):
+def test_batched_parameters_from_table(tmp_path):
     path = tmp_path / "nb.json"
-    assert autotune.pick_batched_nb(str(path)) == autotune.BATCHED_DEFAULT
-    path.write_text(json.dumps({"orders": {}, "batched": {"nb": 32}}))
-    assert autotune.pick_batched_nb(str(path)) == 32
+    assert autotune.pick_batched(str(path)) == autotune.BATCHED_DEFAULT
+    path.write_text(json.dumps({"orders": {}, "batched": {"nb": 32, "block": 16, "wg_per_cu": 2}}))
+    assert autotune.pick_batched(str(path)) == {"nb": 32, "block": 16, "wg_per_cu": 2}
+    path.write_text(json.dumps({"batched": {"nb": 0, "block": 64, "wg_per_cu": 3}}))
+    assert autotune.pick_batched(str(path))["nb"] == 0
+    # an entry without the shape parameters falls back to the defaults
     path.write_text(json.dumps({"batched": {"nb": 0}}))
-    assert autotune.pick_batched_nb(str(path)) == 0
+    assert autotune.pick_batched(str(path)) == autotune.BATCHED_DEFAULT
+
+
+def test_batched_candidates_cover_widths_and_shapes():
+    c = autotune.BATCHED_CANDIDATES
+    assert {nb for nb, _, _ in c} == {0, 32, 64, 128}
+    assert {blk for _, blk, _ in c} == {16, 32, 64}
+    assert {w for _, _, w in c} == {2, 3}
+    assert len(set(c)) == len(c)

@@ -39,10 +39,12 @@ def check_pencil(A0, B0, got, ref=None, upto=None):
             assert d[key] <= TOL, (n, key, d)
 
 
-def test_batched_parity_mixed_orders():
+@pytest.mark.parametrize("nb", [None, 0])
+def test_batched_parity_mixed_orders(nb):
+    """Tuned panel width, and nb = 0: one panel over each whole pencil."""
     sizes = [3, 4, 5, 7, 9, 16, 17, 31, 33, 40, 64, 65, 80, 100, 127, 130]
     pencils = [inputs.random_pencil(n, seed=500 + n) for n in sizes]
-    outs, info = run_batched(pencils)
+    outs, info = run_batched(pencils, nb=nb)
     assert (info == 0).all()
     for (A0, B0), got in zip(pencils, outs):
         check_pencil(A0, B0, got, oracle.basic_ht(A0, B0)[:4])
@@ -67,8 +69,10 @@ def test_batched_pencil_stats():
         assert st.shape == (len(sizes), 8)
         assert (st[:, 0] >= 0).all() and (st[:, 1] >= st[:, 0]).all()
         # phase times are parts of the pencil's span
-        assert (st[:, 4:7] >= 0).all() and (st[:, 4:7].sum(axis=1) <= st[:, 1] - st[:, 0]).all()
-        for n, (t0, t1, panels, ir) in zip(sizes, st[:, :4]):
+        assert (st[:, 4:8] >= 0).all() and (st[:, 4:8].sum(axis=1) <= st[:, 1] - st[:, 0]).all()
+        for n, (t0, t1, panels, ir), t_retri in zip(sizes, st[:, :4], st[:, 7]):
+            # every panel but the last re-triangularises B
+            assert (t_retri > 0) == (panels > 1), (n, panels, t_retri)
             if n <= 2:
                 assert panels == 0 and ir == 0
             elif strict:
@@ -79,15 +83,17 @@ def test_batched_pencil_stats():
                 assert 1 <= panels <= n - 2 and ir >= 0
 
 
-@pytest.mark.parametrize("nb", [16, 64])
-def test_batched_panel_widths(nb):
+@pytest.mark.parametrize("nb,block,wpc", [(16, 32, 3), (64, 32, 3), (64, 16, 2), (32, 64, 1),
+                                          (16, 1, 3)])
+def test_batched_panel_widths(nb, block, wpc):
     """Panels of nb columns: every panel that ends before the last column is
     absorbed and B's trailing block is re-triangularised (blocked Householder
-    QR, 32 reflectors per block, applied to A and Q); parity with the oracle
-    for pencils of one, two and several panels."""
+    QR, `block` reflectors per block, applied to A and Q); parity with the
+    oracle for pencils of one, two and several panels, on 1 to 3 resident
+    workgroups per compute unit."""
     sizes = [nb - 3, nb + 5, 2 * nb + 1, 130, 200]
     pencils = [inputs.random_pencil(n, seed=3000 + n) for n in sizes]
-    outs, info = run_batched(pencils, nb=nb)
+    outs, info = run_batched(pencils, nb=nb, block=block, wg_per_cu=wpc)
     assert (info == 0).all()
     for (A0, B0), got in zip(pencils, outs):
         check_pencil(A0, B0, got, oracle.basic_ht(A0, B0)[:4])
