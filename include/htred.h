@@ -174,10 +174,21 @@ int ht_reduce(double *A, double *B, double *Q, double *Z, int64_t n,
  *             nb = 0 (or opt NULL) runs one panel over each whole pencil.
  *             A panel that ends before the last column is absorbed and B's
  *             trailing block is re-triangularised by a blocked Householder
- *             QR whose transformations go to A and Q.
+ *             QR (batch_block reflectors per block) whose transformations go
+ *             to A and Q.  batch_wg_per_cu workgroups per compute unit stay
+ *             resident and take pencils, largest order first.
  * No host synchronisation and no allocation inside: the call can be
- * captured in a hipGraph.  workspace must hold
- * ht_batched_workspace_size(batch, nmax, opt) bytes.
+ * captured in a hipGraph.  workspace (256-byte aligned) must hold
+ * ht_batched_workspace_size(batch, nmax, opt) bytes for the same options:
+ * one scratch area per resident workgroup (ht_batched_workspace_size
+ * returns 0 for invalid sizes or options).
+ * Returns -1 for batch < 0, -2 for a NULL n_dev, -3 for a NULL A_dev or
+ * B_dev, -5 for a NULL Q_dev or Z_dev, -7 for a NULL ld_dev, -8 for a NULL
+ * info_dev, -9 for nmax outside 0..512, -10 for invalid options,
+ * HT_ERR_UNSUPPORTED for a split precision, HT_ERR_WORKSPACE for a missing,
+ * misaligned or too small workspace, HT_ERR_HIP if the launch fails.  A
+ * pencil whose order, leading dimension or pointers are invalid gets
+ * info = -1 and is left untouched.
  */
 size_t ht_batched_workspace_size(int32_t batch, int32_t nmax, const ht_options *opt);
 int ht_reduce_batched(int32_t batch, const int32_t *n_dev,

@@ -5,19 +5,26 @@
 // Each pencil (order n <= 512) is reduced by one 256-thread workgroup with
 // Algorithm 1: the panel reduction of Sec. 3.2 (column update a, left
 // reflector b, factored solve with iterative refinement c, opposite
-// reflector and Y column d) over all columns as one panel, followed by an
-// absorption in which the accumulated block reflectors
+// reflector and Y column d) over panels of nb columns (nb = 0: one panel over
+// all columns), each followed by an absorption in which the accumulated
+// block reflectors
 //   Q = I - U S U^T,  Z = I - V T V^T  (Sec. 2.4)
-// are applied to B, Q, Z and the not yet reduced part of A as plain dense
+// are applied to B, Q, Z and the not yet reduced part of A as dense
 // products.  Within one panel B is never modified (Sec. 3.2), so its solves
-// use the triangular input B; after the last column the two-sided product
-// (I - U S^T U^T) B (I - V T V^T) is triangular up to rounding (Lemma 2.1
-// for every reduced column), and its strict lower part is set to zero as in
-// Algorithm 2.  When iterative refinement fails for column j (Algorithm 1),
-// the column is restored, the j-s accumulated pairs are absorbed in the
-// same way, the trailing block B(j+1:n, j+1:n) is brought back to
-// triangular form by a Householder QR whose transformations are applied to
-// A (rows j+1..n-1) and Q, and a new panel starts at column j.
+// use the triangular B the panel started from; after the panel the two-sided
+// product (I - U S^T U^T) B (I - V T V^T) is triangular up to rounding in the
+// panel's columns (Lemma 2.1), whose strict lower parts are set to zero as
+// in Algorithm 2, and full in its trailing block.  That block is brought
+// back to triangular form by a blocked Householder QR whose transformations
+// also go to A (rows j+1..n-1) and Q; the next panel starts at the next
+// column.  When iterative refinement fails for column j (Algorithm 1), the
+// column is restored and the panel ends there in the same way.  The banded
+// chains of Sec. 3.3 are not used: for n <= 512 and nb = 64 the trailing
+// block is a few panels wide, where a dense QR costs about as much.
+//
+// Dense products run on FP64 matrix cores (v_mfma_f64_16x16x4f64), one
+// 32 x 32 output tile per wavefront at a time; matrix-vector products and
+// the triangular solve use the vector units with LDS staging.
 //
 // Scheduling: a one-workgroup kernel sorts the pencils by decreasing order
 // (counting sort on n) and resets the work counter; the persistent kernel's
