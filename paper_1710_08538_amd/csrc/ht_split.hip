@@ -34,8 +34,9 @@
 // eight entries each, the exponent from a four-lane max), then runs the
 // levels' MFMAs from LDS.
 //
-// MFMA operand layouts (lane l of the wavefront):
-//   v_mfma_f32_16x16x16_bf16:  A[l%16][4(l/16) + 0..3],  B[4(l/16) + 0..3][l%16]
+// MFMA operand layouts (lane l of the wavefront), one instruction per
+// 32-digit chunk in both formats:
+//   v_mfma_f32_16x16x32_bf16:  A[l%16][8(l/16) + 0..7],  B[8(l/16) + 0..7][l%16]
 //   v_mfma_f32_16x16x32_fp8:   A[l%16][8(l/16) + 0..7],  B[8(l/16) + 0..7][l%16]
 //   result register q:         C[4(l/16) + q][l%16]
 #include "ht_device.h"
@@ -49,24 +50,27 @@ constexpr int SBM = 64;   // tile rows
 constexpr int SBN = 64;   // tile columns
 constexpr int SKC = 32;   // contraction chunk
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Digit formats.  RS: bytes per LDS row of one slice (SKC digits + padding,
-// a multiple of 8 so every fragment read is an aligned 8-byte load).
+// a multiple of 8 so every fragment is read with aligned 8-byte loads; two
+// of them for the 16 bytes of eight BF16 digits).  Frag: one lane's operand.
 template <int FMT>
 struct Fmt;
 template <>
 struct Fmt<0> {  // BF16 digits, 7 bits + sign
   static constexpr int bits = 7;
-  static constexpr int kstep = 16;
+  static constexpr int kstep = 32;
   static constexpr int RS = (SKC + 4) * 2;
+  typedef uint4 Frag;
 };
 template <>
 struct Fmt<1> {  // FP8 E4M3 digits, 4 bits + sign
   static constexpr int bits = 4;
   static constexpr int kstep = 32;
   static constexpr int RS = SKC + 8;
+  typedef uint2 Frag;
 };
 
 constexpr int kSliceBytes = 36864;  // per operand: 8 BF16 slices or 14 FP8 slices
@@ -145,13 +149,26 @@ __device__ __forceinline__ int split_row(double (&x)[8], int ns, unsigned char* 
   return e;
 }
 
+// One lane's operand from a slice row (8-byte aligned).
 template <int FMT>
-__device__ __forceinline__ v4f mfma_digits(uint2 a, uint2 b, v4f c);
+__device__ __forceinline__ typename Fmt<FMT>::Frag load_frag(const unsigned char* p);
+template <>
+__device__ __forceinline__ uint4 load_frag<0>(const unsigned char* p) {
+  const uint2 lo = *(const uint2*)p, hi = *(const uint2*)(p + 8);
+  return make_uint4(lo.x, lo.y, hi.x, hi.y);
+}
+template <>
+__device__ __forceinline__ uint2 load_frag<1>(const unsigned char* p) {
+  return *(const uint2*)p;
+}
+
+template <int FMT>
+__device__ __forceinline__ v4f mfma_digits(typename Fmt<FMT>::Frag a, typename Fmt<FMT>::Frag b, v4f c);
 
 template <>
-__device__ __forceinline__ v4f mfma_digits<0>(uint2 a, uint2 b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(v4s, a),
-                                                   __builtin_bit_cast(v4s, b), c, 0, 0, 0);
+__device__ __forceinline__ v4f mfma_digits<0>(uint4 a, uint4 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
 }
 template <>
 __device__ __forceinline__ v4f mfma_digits<1>(uint2 a, uint2 b, v4f c) {
@@ -235,11 +252,12 @@ __global__ __launch_bounds__(256) void k_split_gemm(SplitArgs a) {
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
           const int kb = (ks * KSTEP + fk) * (FMT == 0 ? 2 : 1);
-          uint2 af[2], bf[2];
+          typedef typename Fmt<FMT>::Frag Frag;
+          Frag af[2], bf[2];
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb) af[rb] = *(const uint2*)(As + (wr + 16 * rb + fr) * RS + kb);
+          for (int rb = 0; rb < 2; ++rb) af[rb] = load_frag<FMT>(As + (wr + 16 * rb + fr) * RS + kb);
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) bf[cb] = *(const uint2*)(Bs + (wc + 16 * cb + fr) * RS + kb);
+          for (int cb = 0; cb < 2; ++cb) bf[cb] = load_frag<FMT>(Bs + (wc + 16 * cb + fr) * RS + kb);
 #pragma unroll
           for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
