@@ -188,7 +188,6 @@ __global__ __launch_bounds__(256) void k_split_gemm(SplitArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r0 = blockIdx.x * SBM, c0 = blockIdx.y * SBN;
   const int ns = a.ns;
-  // loader role: row (column) lr of the tile, entries 8 q4 .. 8 q4 + 7 of the chunk
   const int lr = tid >> 2, q4 = tid & 3;
   // MFMA role: wavefront quarter (wr, wc), lane row/column within a block
   const int wr = (wv & 1) * 32, wc = (wv >> 1) * 32;
@@ -202,34 +201,35 @@ __global__ __launch_bounds__(256) void k_split_gemm(SplitArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) c64[rb][cb][q] = 0.0;
 
-  for (int k0 = 0; k0 < a.k; k0 += SKC) {
-    // ---- load and split the chunk of op(A) (row r0+lr) and op(B) (column c0+lr)
-    {
-      double x[8];
-      const int gr = r0 + lr;
+  // loader role: row r0+lr of op(A) and column c0+lr of op(B), entries
+  // 8 q4 .. 8 q4 + 7 of a chunk; the next chunk's entries are loaded while
+  // the current chunk's MFMAs run
+  const int gr = r0 + lr, gc = c0 + lr;
+  double xa[8], xb[8];
+  auto load_chunk = [&](int k0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kk = k0 + 8 * q4 + u;
-        x[u] = (gr < a.m && kk < a.k)
-                   ? (TA ? a.A[(size_t)kk + (size_t)gr * a.lda] : a.A[(size_t)gr + (size_t)kk * a.lda])
-                   : 0.0;
-      }
-      const int e = split_row<FMT>(x, ns, AD + lr * RS + 8 * q4 * (FMT == 0 ? 2 : 1));
+    for (int u = 0; u < 8; ++u) {
+      const int kk = k0 + 8 * q4 + u;
+      xa[u] = (gr < a.m && kk < a.k)
+                  ? (TA ? a.A[(size_t)kk + (size_t)gr * a.lda] : a.A[(size_t)gr + (size_t)kk * a.lda])
+                  : 0.0;
+      xb[u] = (gc < a.n && kk < a.k)
+                  ? (TB ? a.B[(size_t)gc + (size_t)kk * a.ldb] : a.B[(size_t)kk + (size_t)gc * a.ldb])
+                  : 0.0;
+    }
+  };
+  load_chunk(0);
+  for (int k0 = 0; k0 < a.k; k0 += SKC) {
+    // ---- split the chunk of op(A) and op(B) into LDS, then fetch the next
+    {
+      const int e = split_row<FMT>(xa, ns, AD + lr * RS + 8 * q4 * (FMT == 0 ? 2 : 1));
       if (q4 == 0) ea[lr] = e;
     }
     {
-      double x[8];
-      const int gc = c0 + lr;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int kk = k0 + 8 * q4 + u;
-        x[u] = (gc < a.n && kk < a.k)
-                   ? (TB ? a.B[(size_t)gc + (size_t)kk * a.ldb] : a.B[(size_t)kk + (size_t)gc * a.ldb])
-                   : 0.0;
-      }
-      const int e = split_row<FMT>(x, ns, BD + lr * RS + 8 * q4 * (FMT == 0 ? 2 : 1));
+      const int e = split_row<FMT>(xb, ns, BD + lr * RS + 8 * q4 * (FMT == 0 ? 2 : 1));
       if (q4 == 0) eb[lr] = e;
     }
+    if (k0 + SKC < a.k) load_chunk(k0 + SKC);
     __syncthreads();
 
     // ---- levels: sum over slice pairs (i, L - i), weight 2^{-b (L + 2)}
