@@ -4,7 +4,8 @@
    whose dropped slice pairs are zero): the emulated product must equal the
    exact product bit for bit.  This pins the MFMA lane layouts, the level
    weights, the per-chunk exponents, all four transposition kernels and
-   ragged tile / chunk tails, for the BF16 and the FP8 digit formats.
+   ragged tile / chunk tails, for the BF16 and the FP8 digit formats, on
+   grids of one tile, of several row tiles and of several column tiles.
 2. Random FP64 operands: the error stays within the bound of the splitting,
    (ns + 5) 2^{-b ns} 2^{e_row + e_col} per contraction index, and it
    shrinks as slices are added.
@@ -65,7 +66,8 @@ def exact_operands(prec, m, k, n, seed):
 
 @pytest.mark.parametrize("prec", [htred.HT_PREC_SPLIT_BF16, htred.HT_PREC_SPLIT_FP8])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
-@pytest.mark.parametrize("m,k,n", [(64, 32, 64), (130, 77, 45), (1, 1, 1), (200, 300, 129)])
+@pytest.mark.parametrize("m,k,n", [(64, 32, 64), (130, 77, 45), (1, 1, 1), (200, 300, 129),
+                                   (40, 96, 300), (64, 256, 256)])
 def test_split_gemm_exact_on_representable_operands(prec, ta, tb, m, k, n):
     A, B = exact_operands(prec, m, k, n, seed=m * 7 + k + n)
     got = run_gemm(A, B, ta, tb, prec, 3)
