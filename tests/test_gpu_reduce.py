@@ -228,7 +228,7 @@ def test_config_n16384_illcond_full_size():
     whole output (products on the device) and sign-normalised parity of the
     first reduced column (H(:, 0) and Q(:, 0:2), which depend on A alone) with
     the Moler-Stewart oracle run for one column.  T and Z entries depend on a
-    numerically singular B and are judged by the invariants only."""
+    numerically singular B and are checked against the invariants only."""
     A0, B0 = inputs.workload("n16384")
     n = A0.shape[0]
     A = htred.to_device_colmajor(A0)
