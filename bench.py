@@ -93,10 +93,15 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
     torch.cuda.synchronize()
     restore()
     torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     t = time.time()
-    plan.run()
+    ev0.record()
+    plan.run()  # on the current stream, which the events bracket
+    ev1.record()
     torch.cuda.synchronize()
     eager_s = time.time() - t
+    launch_ms = ev0.elapsed_time(ev1)
     ps = plan.pencil_stats().numpy()
     lat_ms = (ps[:, 1] - ps[:, 0]) / 1e6
     big = np.asarray(sizes) >= 480
@@ -123,6 +128,16 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
         for k in worst:
             worst[k] = max(worst[k], float(inv[k]))
     fl = float(sum(39.0 * float(n) ** 3 for n in sizes))
+    # roofline of the launch: the bytes every reduced column must move (A's
+    # trailing block for Y = A v, 8 m^2, and B's triangle for the solve and
+    # the residual, 8 m^2; m = n - j - 1) against the HBM peak
+    alg = float(sum(16.0 * (n - 1) * n * (2 * n - 1) / 6.0 for n in sizes))
+    ach = alg / (launch_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS,
+            "traffic": measured_traffic("batched", {"nb": plan.nb, "block": plan.block,
+                                                    "wg_per_cu": plan.wg_per_cu}),
+            "kernel": "htk::k_batched", "launch_ms": launch_ms, "algorithmic_bytes": alg}
     return {"pencils": count, "orders": "U{32..512}", "seed": seed, "panel_width": plan.nb,
             "retriangularise_block": plan.block, "workgroups_per_cu": plan.wg_per_cu,
             "ms": 1000.0 * eager_s, "pencils_per_s": count / eager_s,
@@ -137,18 +152,18 @@ def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
                                                    ("retriangularise", 7))}
                                      if big.any() else None),
             "checked_sample": len(range(0, count, 32)), "invariants_ok": ok,
-            "backward_error_max": worst}
+            "backward_error_max": worst, "roofline": roof}
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "hbm_traffic.json")
 
 
-def measured_traffic(cls):
+def measured_traffic(cls, params=None):
     """HBM bytes per launch of the kernel class `cls` from the committed PMC
     counts (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of
-    known size), or None if there are none or the kernel's source changed
-    since they were taken."""
+    known size), or None if there are none, the kernel's source changed
+    since they were taken, or they were taken with other parameters."""
     try:
         with open(TRAFFIC_FILE) as f:
             table = json.load(f)
@@ -156,6 +171,8 @@ def measured_traffic(cls):
         return None
     ent = table.get("classes", {}).get(cls)
     if not ent:
+        return None
+    if params is not None and ent.get("params") != params:
         return None
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), ent["source"])
     try:
