@@ -223,8 +223,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the single-pencil reduction is not "
-              "sharded across GPUs); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the single-pencil reduction is not sharded "
+              "across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
