@@ -41,3 +41,19 @@ def test_batched_candidates_cover_widths_and_shapes():
     assert {blk for _, blk, _ in c} == {16, 32, 64}
     assert {w for _, _, w in c} == {2, 3}
     assert len(set(c)) == len(c)
+
+
+def test_committed_table_holds_the_batched_search():
+    """The shipped table's batched entry is the fastest of its own recorded
+    timings, over every candidate the tuner searches."""
+    with open(autotune.TABLE) as f:
+        data = json.load(f)
+    ent = data["batched"]
+    secs = ent["seconds"]
+    assert set(secs) == {autotune.batched_key(*c) for c in autotune.BATCHED_CANDIDATES}
+    best = min(secs, key=secs.get)
+    assert best == autotune.batched_key(ent["nb"], ent["block"], ent["wg_per_cu"])
+    assert autotune.pick_batched() == {k: ent[k] for k in ("nb", "block", "wg_per_cu")}
+    # the single-pencil table: one width per order, from its own timings
+    for n, e in data["orders"].items():
+        assert int(e["nb"]) == int(min(e["seconds"], key=e["seconds"].get)), n
