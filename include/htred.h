@@ -92,7 +92,8 @@ typedef struct {
 } ht_options;
 
 /* flags */
-#define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs) */
+#define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs;
+                                   allocates a 4-byte device flag) */
 #define HT_FLAG_PROFILE      2  /* time kernel classes with HIP events (stats) */
 #define HT_FLAG_SOLVE_SOLO   4  /* triangular solves on one workgroup, without
                                    helper workgroups (slower; for testing) */
@@ -149,9 +150,10 @@ size_t ht_workspace_size(int64_t n, const ht_options *opt);
  *         256-byte aligned, owned by the caller.
  *   stream hipStream_t (void*), NULL = default stream.
  *
- * The call synchronises `stream` once per column whose solve needs
- * iterative refinement and once per reflector pair to read the refinement
- * verdict, so it is not graph-capturable; ht_reduce_batched is.
+ * The call synchronises `stream` once per reflector pair and once per
+ * iterative-refinement step to read the refinement verdict (through a
+ * 256-byte pinned host buffer that the first call allocates once), so it
+ * is not graph-capturable; ht_reduce_batched is.
  * Results are deterministic: no floating-point atomics are used.
  */
 int ht_reduce(double *A, double *B, double *Q, double *Z, int64_t n,
