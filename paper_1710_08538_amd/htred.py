@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(_HERE, "_build", "libhtred.so")
 HT_QZ_IDENTITY, HT_QZ_ACCUMULATE, HT_QZ_NONE = 0, 1, 2
 HT_PREC_FP64, HT_PREC_SPLIT_BF16, HT_PREC_SPLIT_FP8 = 0, 1, 2
 HT_FLAG_CHECK_FINITE = 1
+# return codes (include/htred.h); negative values name an invalid argument
+HT_OK, HT_ERR_HIP, HT_ERR_WORKSPACE, HT_ERR_NONFINITE, HT_ERR_UNSUPPORTED, HT_ERR_NOLIB = range(6)
 HT_FLAG_PROFILE = 2
 HT_FLAG_SOLVE_SOLO = 4
 PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain", "sweep")

@@ -161,3 +161,44 @@ def test_check_argument_validation(L):
     assert L.ht_check(z, z, z, z, z, z, 4, 4, None, z) == -9
     assert L.ht_check(z, z, z, z, z, z, 4, 4, out, z) == -1
     assert L.ht_check(z, z, z, z, z, z, 0, 1, out, z) == 0 and list(out) == [0.0] * 4
+
+
+def _gpu_count():
+    import torch
+    return torch.cuda.device_count()  # counts devices without initialising HIP
+
+
+@pytest.mark.skipif(_gpu_count() > 0, reason="the calls use placeholder pointers: only "
+                    "meaningful (and only safe) where no GPU is visible")
+def test_compute_calls_fail_without_a_gpu():
+    """No CPU fallback: with no device, the compute entry points fail with
+    HT_ERR_HIP instead of computing anything on the host.  Run in a child
+    process with every GPU hidden as well."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys\n"
+        "sys.path.insert(0, %r)\n"
+        "from paper_1710_08538_amd import htred\n"
+        "L = htred.lib()\n"
+        "p = [ctypes.c_void_p(64 * (i + 1)) for i in range(4)]\n"
+        "print(L.ht_reduce(p[0], p[1], p[2], p[3], 4, 4, 4, 4, 4, None, None, None, 0, None))\n"
+        "print(L.ht_wy_gemm(0, 0, 0, 0, 4, 4, 4, 1.0, p[0], 4, p[1], 4, 0.0, p[2], 4, None))\n"
+    ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", CUDA_VISIBLE_DEVICES="-1",
+               ROCR_VISIBLE_DEVICES="-1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0, r.stderr
+    from paper_1710_08538_amd import htred
+    assert [int(x) for x in r.stdout.split()] == [htred.HT_ERR_HIP, htred.HT_ERR_HIP]
+
+
+def test_return_codes_match_the_header():
+    from paper_1710_08538_amd import htred
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "htred.h")).read()
+    codes = dict(re.findall(r"#define (HT_(?:OK|ERR_[A-Z]+))\s+(\d+)", hdr))
+    assert len(codes) == 6
+    for name, val in codes.items():
+        assert getattr(htred, name) == int(val), name
