@@ -268,3 +268,31 @@ def test_ht_check_matches_host_invariants_and_sees_a_planted_error():
     dev2 = htred.check(Ad, Bd, A, B, Q, Z)
     assert abs(dev2["bwd_A"] - 1e-6) <= 1e-12, dev2
     assert dev2["bwd_B"] == dev["bwd_B"] and dev2["orth_Q"] == dev["orth_Q"]
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        g = json.load(f)
+    A = np.asfortranarray(np.array(g["A"], dtype=np.float64))
+    B = np.asfortranarray(np.array(g["B"], dtype=np.float64))
+    return A, B, tuple(np.array(g[k], dtype=np.float64) for k in ("H", "T", "Q", "Z"))
+
+
+@pytest.mark.parametrize("form", ["reduce", "batched"])
+def test_golden_hessenberg_3x3_identity_B(form):
+    """The hand-worked 3 x 3 case of tests/golden: both entry points give its
+    H, T, Q, Z up to the free column signs."""
+    A0, B0, ref = _golden("hessenberg_3x3_identity_B.json")
+    if form == "reduce":
+        got, _ = run_gpu(A0, B0, nb=1)
+    else:
+        print("ht_reduce_batched golden 3x3", flush=True)
+        A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+        Qs, Zs, info = htred.reduce_batched([A], [B])
+        torch.cuda.synchronize()
+        assert int(info[0]) == 0
+        got = (A.cpu().numpy(), B.cpu().numpy(), Qs[0].cpu().numpy(), Zs[0].cpu().numpy())
+    assert_parity(ref, got, A0, B0, tol=1e-15)

@@ -246,3 +246,23 @@ def test_planted_mistakes_are_caught():
         inv = checks.invariants(A, B, *bad)
         d = checks.compare(ref, bad, A, B)
         assert (not checks.invariants_ok(inv, n)) or max(d["max_H"], d["max_Q"], d["max_Z"]) > 1e-9
+
+
+def test_golden_hessenberg_3x3_identity_B():
+    """A worked 3 x 3 case with a closed form (tests/golden, derivation and
+    citation inside the fixture): both oracles reproduce the hand-computed
+    H, T, Q, Z up to the column signs the problem leaves free."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "hessenberg_3x3_identity_B.json")
+    with open(path) as f:
+        g = json.load(f)
+    A = np.asfortranarray(np.array(g["A"], dtype=np.float64))
+    B = np.asfortranarray(np.array(g["B"], dtype=np.float64))
+    ref = tuple(np.array(g[k], dtype=np.float64) for k in ("H", "T", "Q", "Z"))
+    assert abs(np.trace(ref[0]) - np.trace(A)) < 1e-14
+    for got in (oracle.basic_ht(A, B)[:4], oracle.ms_ht(A, B)):
+        d = checks.compare(ref, got, A, B)
+        for key in ("max_H", "max_T", "max_Q", "max_Z"):
+            assert d[key] < 1e-15, (key, d)
