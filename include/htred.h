@@ -173,7 +173,8 @@ int ht_reduce(double *A, double *B, double *Q, double *Z, int64_t n,
  *   nmax      host-side upper bound of n_dev (sizes the launch);
  *   opt       max_ir, ir_tol_factor and seed as in ht_reduce; nb is the panel
  *             width of every pencil's reduction as given (1..128), and
- *             nb = 0 (or opt NULL) runs one panel over each whole pencil.
+ *             nb = 0 runs one panel over each whole pencil; opt NULL takes
+ *             ht_default_options (nb 64, batch_block 32, batch_wg_per_cu 3).
  *             A panel that ends before the last column is absorbed and B's
  *             trailing block is re-triangularised by a blocked Householder
  *             QR (batch_block reflectors per block) whose transformations go

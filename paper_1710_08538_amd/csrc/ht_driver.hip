@@ -886,9 +886,9 @@ int ht_reduce_batched(int32_t batch, const int32_t* n_dev, double* const* A_dev,
       ws_bytes < batched_workspace_bytes(batch, std::max(nmax, 1), o.batch_wg_per_cu))
     return HT_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  // the panel width of the batched form is the caller's nb as given: 0 (or
-  // no options) means one panel over each whole pencil
-  const int nb = (opt && opt->nb > 0) ? o.nb : 0;
+  // the panel width of the batched form is the caller's nb as given (0: one
+  // panel over each whole pencil); no options means the defaults
+  const int nb = opt ? std::max(opt->nb, 0) : o.nb;
   batched_reduce(st, batch, n_dev, A_dev, B_dev, Q_dev, Z_dev, ld_dev, info_dev,
                  std::max(nmax, 1), nb, o.batch_block, o.batch_wg_per_cu, o.max_ir,
                  o.ir_tol_factor, o.seed, workspace);

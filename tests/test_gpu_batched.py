@@ -228,3 +228,35 @@ def test_batched_full_workload():
         A0, B0 = pencils[i]
         got = tuple(M.cpu().numpy() for M in (As[i], Bs[i], Qs[i], Zs[i]))
         check_pencil(A0, B0, got, oracle.ms_ht(A0, B0)[:4])
+
+
+def test_null_options_take_the_defaults():
+    """ht_reduce_batched with opt = NULL runs the library defaults (panel
+    width 64, QR block 32, 3 workgroups per CU): bitwise the same as those
+    options passed explicitly."""
+    import ctypes
+    sizes = [70, 130, 5, 200]
+    pencils = [inputs.random_pencil(n, seed=4100 + n) for n in sizes]
+    outs = []
+    for use_null in (False, True):
+        print("ht_reduce_batched sizes=%s null_options=%s" % (sizes, use_null), flush=True)
+        As, Bs = to_dev(pencils)
+        Qs = [htred.colmajor_empty(A.shape[0]) for A in As]
+        Zs = [htred.colmajor_empty(A.shape[0]) for A in As]
+        plan = htred.BatchedPlan(As, Bs, Qs, Zs, nb=64, block=32, wg_per_cu=3)
+        if not use_null:
+            plan.run()
+        else:
+            L = htred.lib()
+            assert L.ht_batched_workspace_size(plan.batch, plan.nmax, None) == plan.ws.numel()
+            s = torch.cuda.current_stream()
+            rc = L.ht_reduce_batched(plan.batch, plan.n.data_ptr(), plan.pA.data_ptr(),
+                                     plan.pB.data_ptr(), plan.pQ.data_ptr(), plan.pZ.data_ptr(),
+                                     plan.ld.data_ptr(), plan.info.data_ptr(), plan.nmax, None,
+                                     plan.ws.data_ptr(), plan.ws.numel(), s.cuda_stream)
+            assert rc == 0
+        torch.cuda.synchronize()
+        assert (plan.info[:len(sizes)].cpu().numpy() == 0).all()
+        outs.append([M.cpu().numpy() for group in (As, Bs, Qs, Zs) for M in group])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
