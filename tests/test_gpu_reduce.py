@@ -296,3 +296,23 @@ def test_golden_hessenberg_3x3_identity_B(form):
         assert int(info[0]) == 0
         got = (A.cpu().numpy(), B.cpu().numpy(), Qs[0].cpu().numpy(), Zs[0].cpu().numpy())
     assert_parity(ref, got, A0, B0, tol=1e-15)
+
+
+@pytest.mark.parametrize("n,nb", [(64, 16), (200, 32)])
+def test_saddle_point_pencils(n, nb):
+    """Test Suite 4's saddle-point pencils: B = diag(I, 0) has n/4 zero
+    pivots, each replaced by 2 u rho ||B||_F (Remark 2.2).  B + Delta_0 is
+    numerically singular, so the check is the invariants (backward errors,
+    orthogonality, exact zeros), for ht_reduce and ht_reduce_batched."""
+    A0, B0 = inputs.saddle_pencil(n, seed=n)
+    got, _ = run_gpu(A0, B0, nb=nb)
+    inv = checks.invariants(A0, B0, *got)
+    assert checks.invariants_ok(inv, n), inv
+    print("ht_reduce_batched saddle n=%d" % n, flush=True)
+    A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    Qs, Zs, info = htred.reduce_batched([A], [B])
+    torch.cuda.synchronize()
+    assert int(info[0]) == 0
+    got = (A.cpu().numpy(), B.cpu().numpy(), Qs[0].cpu().numpy(), Zs[0].cpu().numpy())
+    inv = checks.invariants(A0, B0, *got)
+    assert checks.invariants_ok(inv, n), inv

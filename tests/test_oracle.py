@@ -266,3 +266,14 @@ def test_golden_hessenberg_3x3_identity_B():
         d = checks.compare(ref, got, A, B)
         for key in ("max_H", "max_T", "max_Q", "max_Z"):
             assert d[key] < 1e-15, (key, d)
+
+
+@pytest.mark.parametrize("n", [8, 24])
+def test_saddle_point_pencils(n):
+    """Test Suite 4's saddle-point pencils (Sec. 4): B = diag(I, 0) has n/4
+    zero pivots, each replaced by 2 u rho ||B||_F (Remark 2.2).  Both
+    oracles stay backward stable and keep the exact zeros."""
+    A, B = inputs.saddle_pencil(n, seed=n)
+    assert np.count_nonzero(np.diag(B) == 0.0) == n - (3 * n) // 4
+    _check_inv(A, B, oracle.basic_ht(A, B))
+    _check_inv(A, B, oracle.ms_ht(A, B))
