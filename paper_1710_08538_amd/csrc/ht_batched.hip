@@ -127,46 +127,6 @@ __device__ __noinline__ void wg_zero_mat(double* X, int m, int n, int ld) {
 // LDS staging area of the pencil workgroup: a vector of up to kBMax entries
 // and a block that holds either 4 columns of an operand (kBMax x 4) or the
 // 64 x 64 diagonal tile of a triangular solve (leading dimension 65).
-// Two block-wide maxima (sums) at once, each over the same tree as
-// block_max (block_sum): one pair of barriers instead of two; sh holds
-// 2 kBNW doubles.
-__device__ __forceinline__ void block_max2(double& a, double& b, double* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  a = wave_max(a);
-  b = wave_max(b);
-  __syncthreads();
-  if (lane == 0) {
-    sh[wv] = a;
-    sh[kBNW + wv] = b;
-  }
-  __syncthreads();
-  double s = 0.0, t = 0.0;
-  for (int i = 0; i < kBNW; ++i) {
-    s = fmax(s, sh[i]);
-    t = fmax(t, sh[kBNW + i]);
-  }
-  a = s;
-  b = t;
-}
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  a = wave_sum(a);
-  b = wave_sum(b);
-  __syncthreads();
-  if (lane == 0) {
-    sh[wv] = a;
-    sh[kBNW + wv] = b;
-  }
-  __syncthreads();
-  double s = 0.0, t = 0.0;
-  for (int i = 0; i < kBNW; ++i) {
-    s += sh[i];
-    t += sh[kBNW + i];
-  }
-  a = s;
-  b = t;
-}
-
 constexpr int kTileLd = 65;
 struct Lds {
   double xs[kBMax];
@@ -524,17 +484,10 @@ struct Pencil {
 
 // Factored solve (Sec. 3.2.2 c): ctil <- (I - U S U^T) ctil (nu reflectors),
 // B(s+1:n, s+1:n) ysol = 2^{-E} ctil, ysol <- (I - V T^T V^T) ysol (kk).
-// unit >= 0: ctil is the unit vector e_unit, so U^T ctil is row `unit` of U
-// (read directly; the product would give the same values).
 __device__ __noinline__ int factored_solve(const Pencil& P, const BWork& w, int s, int kk, int nu, double* ctil,
-                              double* ysol, double* r, double* dg, int* shi, Lds& ls, int unit) {
+                              double* ysol, double* r, double* dg, int* shi, Lds& ls) {
   const int L = P.n - s - 1;
-  if (unit >= 0) {
-    for (int c = threadIdx.x; c < nu; c += kBT) w.tk[c] = w.U[unit + (size_t)c * w.ld];
-    __syncthreads();
-  } else {
-    wg_gemv_t(L, nu, 1.0, w.U, w.ld, ctil, 0.0, w.tk, ls);
-  }
+  wg_gemv_t(L, nu, 1.0, w.U, w.ld, ctil, 0.0, w.tk, ls);
   wg_trmv_small(false, nu, w.S, w.ld, w.tk, 1.0, w.tk2, ls);
   wg_gemv_n(L, nu, -1.0, w.U, w.ld, w.tk2, 1, 1.0, ctil, ls);
   const double* Bp = P.B + (size_t)(s + 1) + (size_t)(s + 1) * P.ld;
@@ -570,7 +523,8 @@ __device__ __noinline__ bool residual(const Pencil& P, const BWork& w, int s, in
     rmax = fmax(rmax, fabs(ri));
     xmax = fmax(xmax, fabs(x[i]));
   }
-  block_max2(rmax, xmax, sh);
+  rmax = block_max(rmax, sh);
+  xmax = block_max(xmax, sh);
   const double ir = safe_scale(rmax), ix = safe_scale(xmax);
   double rs = 0.0, xs = 0.0;
   for (int i = threadIdx.x; i < m; i += kBT) {
@@ -578,7 +532,8 @@ __device__ __noinline__ bool residual(const Pencil& P, const BWork& w, int s, in
     rs = fma(a, a, rs);
     xs = fma(b, b, xs);
   }
-  block_sum2(rs, xs, sh);
+  rs = block_sum(rs, sh);
+  xs = block_sum(xs, sh);
   const double rn = sqrt(rs) / ir, xn = sqrt(xs) / ix;
   return rn <= tol_factor * kUnitRoundoff * normB * xn;
 }
@@ -748,7 +703,7 @@ __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const 
       if (threadIdx.x == 0) w.ctil[kk] = 1.0;
       __syncthreads();
       tc = (int64_t)wall_clock64();
-      int E = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.ysol, r, dg, shi, ls, kk);
+      int E = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.ysol, r, dg, shi, ls);
       tick(cnt.t_solve);
       double* x = w.ysol + kk;
       bool ok = true;
@@ -759,7 +714,7 @@ __device__ PencilCount reduce_pencil(const BatchArgs& a, const Pencil& P, const 
           for (int i = threadIdx.x; i < L; i += kBT) w.ctil[i] = (i < kk) ? 0.0 : w.rv[i - kk];
           __syncthreads();
           tc = (int64_t)wall_clock64();
-          const int E2 = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.dsol, r, dg, shi, ls, -1);
+          const int E2 = factored_solve(P, w, s, kk, kk + 1, w.ctil, w.dsol, r, dg, shi, ls);
           tick(cnt.t_solve);
           for (int i = threadIdx.x; i < m; i += kBT) x[i] = ldexp(x[i], -E2) + w.dsol[kk + i];
           __syncthreads();
@@ -834,7 +789,7 @@ __global__ __launch_bounds__(1024) void k_batched_order(BatchArgs a) {
 // each is register-allocated on its own (no spills inside their loops).
 __global__ __launch_bounds__(kBT, 3) void k_batched(BatchArgs a) {
   __shared__ double r[kBMax];
-  __shared__ double sh[2 * kBNW];
+  __shared__ double sh[kBNW];
   __shared__ int shi[2];
   __shared__ Lds ls;
   double* dg = ls.bs;  // the solve's diagonal tile shares the operand block
