@@ -123,11 +123,15 @@ typedef struct {
     int64_t prof_launches[HT_PROF_NCLASS]; /* launches timed */
 } ht_stats;
 
-/* Fills *opt with the defaults listed above.  Returns 0. */
+/* Fills *opt with the defaults listed above: the refinement limits of
+ * Sec. 2.3 and Sec. 3.2.2 (at most 10 steps, tolerance 2 u ||B||_F) and the
+ * panel width of Sec. 3.2 / Sec. 3.3 (64).  Returns 0 (-1 for a NULL opt). */
 int ht_default_options(ht_options *opt);
 
 /* Device workspace (bytes) ht_reduce needs for order n with these options
- * (opt may be NULL for the defaults). */
+ * (opt may be NULL for the defaults): the panel factors U, V, Y, S, T of
+ * Sec. 3.2 and the window transforms of the absorption chains of Sec. 3.3.
+ * Returns 0 for invalid options or n outside 0..2^30. */
 size_t ht_workspace_size(int64_t n, const ht_options *opt);
 
 /*
@@ -233,7 +237,8 @@ int ht_check(const double *A0, const double *B0, const double *H, const double *
              void *stream);
 
 /*
- * ht_wy_gemm -- one product of the WY updates as ht_reduce computes it for
+ * ht_wy_gemm -- one product of the block-reflector (WY) updates of Sec. 2.4
+ * and Sec. 3.3 (window applications, rank-k corrections) as ht_reduce computes it for
  * `prec`:  C = alpha op(A) op(B) + beta C  (op(X) = X or X^T per transA /
  * transB != 0), op(A) m x k, op(B) k x n, C m x n; device pointers,
  * column-major, FP64 storage; beta == 0 ignores C's contents.  Exposed so
@@ -248,10 +253,12 @@ int ht_wy_gemm(int32_t prec, int32_t n_slices, int32_t transA, int32_t transB,
                const double *A, int64_t lda, const double *B, int64_t ldb,
                double beta, double *C, int64_t ldc, void *stream);
 
-/* Human-readable name of a return code. */
+/* Library utility (no passage of the paper): human-readable name of a
+ * return code; never NULL. */
 const char *ht_strerror(int code);
 
-/* Library version string, e.g. "htred 0.1 gfx950". */
+/* Library utility (no passage of the paper): version string, e.g.
+ * "htred 0.1 gfx950". */
 const char *ht_version(void);
 
 #ifdef __cplusplus

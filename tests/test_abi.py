@@ -202,3 +202,25 @@ def test_return_codes_match_the_header():
     assert len(codes) == 6
     for name, val in codes.items():
         assert getattr(htred, name) == int(val), name
+
+
+def test_every_declaration_is_documented_and_cited():
+    """Each entry point in include/htred.h has its own comment block; those
+    that compute something cite the passage of the paper they follow, the
+    utilities say that they have none."""
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "htred.h")).read()
+    cite = re.compile(r"(Sec\. [0-9]|Algorithm [0-9]|Theorem [A-Z0-9]|Remark [0-9]|Lemma [0-9])")
+    names = []
+    for m in re.finditer(r"^(?:int|size_t|const char \*)\s*(ht_\w+)\(", hdr, re.M):
+        name = m.group(1)
+        names.append(name)
+        before = hdr[:m.start()]
+        end = before.rfind("*/")
+        assert end >= 0 and len(before) - end < 400, name  # a comment right above
+        block = before[before.rfind("/*", 0, end):end]
+        if name in ("ht_strerror", "ht_version"):
+            assert "no passage of the paper" in block, name
+        else:
+            assert cite.search(block), name
+    assert len(names) == 10
