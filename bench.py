@@ -16,9 +16,17 @@ run after the timed ones with every launch bracketed by HIP events on the
 library's stream (the timed steps run without events); achieved =
 algorithmic work of that class / its summed launch durations.
 
-cpu_baseline: the CPU oracle (Moler-Stewart, plain C, one thread) on the
-first columns of the same pencil, extrapolated to the whole reduction by its
-per-column rotation count.
+cpu_baseline: the O(n^3) CPU oracle (O-fast, plain C with OpenMP on every
+host core) on the first columns of the same pencil for a bounded time,
+extrapolated to the whole reduction by the oracle's modelled work per
+column (labelled as extrapolated).
+
+Budget: the whole run fits --budget-s seconds of wall time (default 450).
+--steps and --warmup are upper bounds; after the first warm-up step the
+number of timed steps is chosen so that the profiled step, the invariant
+check, the CPU baseline and the forms still fit, dropping the forms (FP8,
+then BF16, then batched) before timing fewer than two steps.  The JSON line
+reports the steps actually timed.
 """
 import argparse
 import hashlib
@@ -41,30 +49,43 @@ def nominal_flops(n):
     return 39.0 * float(n) ** 3
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A0, B0, target_s):
-    """Time the Moler-Stewart oracle on a bounded prefix of the reduction."""
+    """The O(n^3) CPU oracle (O-fast: Algorithm 2's reflector pair per column
+    with B kept triangular by Givens QR updates; plain C, OpenMP on every host
+    core) on the first columns of the same pencil, for about `target_s`
+    seconds of its column loop, extrapolated to the whole reduction by the
+    oracle's modelled flops per column.  The early columns are the largest,
+    so the extrapolation is by work, not by column count."""
     import oracle
     n = A0.shape[0]
-    total_rot = (n - 2) * (n - 1) / 2.0
-    c = 1
-    t = time.time()
-    oracle.ms_ht(A0, B0, ncols=c)
-    dt = time.time() - t
-    # grow the prefix while the estimated time stays under the target
-    per_col = dt
-    if n < 8192 and per_col * 2 < target_s:
-        c = max(1, min(n - 2, int(target_s / max(per_col, 1e-3))))
-        t = time.time()
-        oracle.ms_ht(A0, B0, ncols=c)
-        dt = time.time() - t
-    sample_rot = sum(n - j - 2 for j in range(c))
-    t_full = dt * total_rot / sample_rot
-    return {"value": nominal_flops(n) / t_full / 1e9, "unit": "GFLOP/s", "cores": 1,
+    threads = os.cpu_count() or 1
+    tm = {"limit_s": float(target_s)}
+    oracle.fast_ht(A0, B0, threads=threads, timing=tm)
+    c = max(tm["columns"], 1)
+    w_sample = oracle.fast_flops(n, c)
+    w_full = oracle.fast_flops(n)
+    t_full = tm["loop_s"] * w_full / w_sample
+    return {"value": nominal_flops(n) / t_full / 1e9, "unit": "GFLOP/s", "cores": threads,
             "kind": "oracle",
-            "sample": ("Moler-Stewart Givens HT reduction (plain C, 1 thread) on the first %d of "
-                       "%d columns of the same pencil in %.1f s; full time %.0f s extrapolated by "
-                       "rotations per column" % (c, n - 2, dt, t_full)),
-            "time_s_extrapolated": t_full}
+            "sample": ("O-fast oracle (Algorithm 2's reflector pair per column, B kept "
+                       "triangular by Givens QR updates; plain C, OpenMP, %d threads on %s) on "
+                       "the first %d of %d columns of the same n=%d pencil: %.1f s; whole "
+                       "reduction EXTRAPOLATED by the oracle's modelled flops per column to "
+                       "%.0f s; value = 39 n^3 nominal flops / that time"
+                       % (threads, cpu_model(), c, n - 2, n, tm["loop_s"], t_full)),
+            "columns_sampled": c, "sample_s": tm["loop_s"], "time_s_extrapolated": t_full,
+            "oracle_gflops_modelled": w_full / t_full / 1e9, "cpu_model": cpu_model()}
 
 
 def batched_form(torch, htred, inputs, checks, count=2048, seed=4):
@@ -206,11 +227,64 @@ def precision_form(torch, htred, checks, A0d, B0d, A, B, Q, Z, ws, nb, name, t_f
             "absorptions": st["absorptions"]}
 
 
+T_START = time.time()
+
+
+class Budget:
+    """Wall-clock budget of the whole run, from process start.  The timed
+    steps are capped so that the run (inputs, warm-up, timed steps, the
+    profiled step, the CPU baseline and the forms measured beside the
+    headline) ends inside it; --steps and --warmup are upper bounds."""
+
+    def __init__(self, total_s, clock=time.time, t0=None):
+        self.total = float(total_s)
+        self.clock = clock
+        self.t0 = T_START if t0 is None else t0
+
+    def left(self):
+        return self.total - (self.clock() - self.t0)
+
+
+def plan_steps(left_s, t_step, steps_cap, warm_cap, tail):
+    """How many extra warm-up steps and timed steps fit in `left_s` seconds
+    after the first warm-up step (which took `t_step`), keeping the time
+    estimated for the optional parts `tail` (list of (name, seconds), most
+    wanted first).  Optional parts are dropped from the end of the list
+    until at least min(2, steps_cap) timed steps fit; at least one step is
+    always timed.  Returns (extra_warmup, steps, kept_tail_names)."""
+    tail = list(tail)
+    want = min(2, steps_cap)
+    while True:
+        avail = left_s - sum(t for _, t in tail)
+        k = int(avail // max(t_step, 1e-9))
+        if k >= want or not tail:
+            break
+        tail.pop()
+    k = max(1, min(steps_cap, k))
+    spare = left_s - sum(t for _, t in tail) - k * t_step
+    extra_w = max(0, min(warm_cap - 1, int(spare // max(t_step, 1e-9))))
+    # extra warm-ups only when every requested timed step already fits
+    if k < steps_cap:
+        extra_w = 0
+    return extra_w, k, [name for name, _ in tail]
+
+
+def upload_colmajor(torch, htred, M):
+    """Host matrix (any numpy layout) -> column-major device tensor; a
+    row-major source is uploaded as is and transposed on the device."""
+    t = torch.from_numpy(M).to("cuda") if M.flags.c_contiguous else torch.as_tensor(M)
+    out = htred.colmajor_empty(M.shape[0], M.shape[1])
+    out.copy_(t)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed steps (upper bound)")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up steps (upper bound, >= 1)")
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall-clock budget of the whole run, from process start")
     ap.add_argument("--workload", default="n16384")
     ap.add_argument("--n", type=int, default=None, help="override the order (same generator)")
     ap.add_argument("--nb", type=int, default=128)
@@ -227,25 +301,31 @@ def main():
               "across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import torch
     from paper_1710_08538_amd import htred, inputs
     from oracle import checks
 
+    budget = Budget(args.budget_s)
+
+    def log(msg):
+        print("bench [%5.1f s left]: %s" % (budget.left(), msg), file=sys.stderr, flush=True)
+
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prec = {"fp64": htred.HT_PREC_FP64, "bf16": htred.HT_PREC_SPLIT_BF16,
             "fp8": htred.HT_PREC_SPLIT_FP8}[args.prec]
-    A0, B0 = inputs.workload(args.workload, n=args.n)
+    A0, B0 = inputs.workload(args.workload, n=args.n, order="C")
     n = A0.shape[0]
-    print("bench: workload %s n=%d nb=%d prec=%s" % (args.workload, n, args.nb, args.prec),
-          file=sys.stderr, flush=True)
-    A0d = htred.to_device_colmajor(A0)
-    B0d = htred.to_device_colmajor(B0)
+    log("workload %s n=%d nb=%d prec=%s generated" % (args.workload, n, args.nb, args.prec))
+    A0d = upload_colmajor(torch, htred, A0)
+    B0d = upload_colmajor(torch, htred, B0)
     A = htred.colmajor_empty(n)
     B = htred.colmajor_empty(n)
     Q = htred.colmajor_empty(n)
     Z = htred.colmajor_empty(n)
     ws = torch.empty(htred.workspace_size(n, nb=args.nb), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    log("inputs resident on the device")
 
     def step(profile):
         A.copy_(A0d)
@@ -253,28 +333,48 @@ def main():
         return htred.reduce(A, B, Q, Z, nb=args.nb, prec=prec, stats=True, workspace=ws,
                             profile=profile)[2]
 
-    for i in range(args.warmup):
-        t = time.time()
+    t = time.time()
+    step(False)
+    torch.cuda.synchronize()
+    t_step = time.time() - t
+    log("warm-up 0 done in %.2f s" % t_step)
+
+    # what must still fit after the timed steps, most wanted first
+    fp64 = prec == htred.HT_PREC_FP64
+    tail = [("profiled_step", 1.1 * t_step + 3.0)]
+    if not args.no_check:
+        tail.append(("check", 8.0))
+    if not args.no_cpu_baseline:
+        tail.append(("cpu_baseline", args.cpu_seconds + 25.0))
+    if not args.no_forms:
+        tail.append(("batched", 40.0))
+        if fp64:
+            tail.append(("precision_bf16", 1.45 * t_step + 10.0))
+            tail.append(("precision_fp8", 1.85 * t_step + 10.0))
+    extra_w, K, kept = plan_steps(budget.left() - 10.0, t_step, max(args.steps, 1),
+                                  max(args.warmup, 1), tail)
+    log("plan: %d more warm-up step(s), %d timed step(s), then %s" % (extra_w, K, kept))
+    for i in range(extra_w):
         step(False)
         torch.cuda.synchronize()
-        print("bench: warmup %d done in %.2f s" % (i, time.time() - t), file=sys.stderr, flush=True)
+        log("warm-up %d done" % (i + 1))
 
     torch.cuda.synchronize()
     t0 = time.time()
     stats = []
-    for i in range(args.steps):
+    for i in range(K):
         stats.append(step(False))
-        print("bench: step %d done" % i, file=sys.stderr, flush=True)
+        log("step %d done" % i)
     torch.cuda.synchronize()
     elapsed = time.time() - t0
-    ms_per_step = 1000.0 * elapsed / args.steps
+    ms_per_step = 1000.0 * elapsed / K
 
     # one more step, outside the timed region, with every launch bracketed by
     # HIP events on the library's stream: per-class device time and work
     t = time.time()
     pstats = [step(True)]
     torch.cuda.synchronize()
-    print("bench: profiled step done in %.2f s" % (time.time() - t), file=sys.stderr, flush=True)
+    log("profiled step done in %.2f s" % (time.time() - t))
 
     # roofline of the dominant kernel class over the profiled step
     ncls = len(htred.PROF_CLASSES)
@@ -290,17 +390,17 @@ def main():
         if name in ("trsv", "trmv", "ygemv"):  # work = algorithmic bytes
             a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e9
             r = {"bound": "hbm", "achieved": a, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-        elif name == "sweep":                  # FP64 MFMA
+        elif name in ("sweep", "wy") and prec == htred.HT_PREC_FP64:  # FP64 MFMA
             a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
             r = {"bound": "mfma", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
-        elif name == "wy" and prec != htred.HT_PREC_FP64:
+        elif name == "wy":
             # split products: every FP64 flop costs ns(ns+1)/2 digit-pair
             # products on the BF16 / FP8 matrix cores
             ns = 8 if prec == htred.HT_PREC_SPLIT_BF16 else 14
             a = prof_work[c] * ns * (ns + 1) / 2 / (prof_ms[c] * 1e-3) / 1e12
             pk = PEAK_BF16_TFLOPS if prec == htred.HT_PREC_SPLIT_BF16 else PEAK_FP8_TFLOPS
             r = {"bound": "mfma", "achieved": a, "peak": pk, "unit": "TFLOP/s"}
-        else:                                  # chains, generic products: FP64 vector ALU
+        else:                                  # chains: FP64 vector ALU
             a = prof_work[c] / (prof_ms[c] * 1e-3) / 1e12
             r = {"bound": "alu", "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
         r["frac"] = r["achieved"] / r["peak"]
@@ -321,17 +421,20 @@ def main():
         "value": nominal_flops(n) / (ms_per_step * 1e-3) / 1e9,
         "unit": "GFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": K,
+        "warmup": 1 + extra_w,
         "ms_per_step": ms_per_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == htred.HT_PREC_FP64 else ("f64-split-" + args.prec),
+        "dtype": "f64" if fp64 else ("f64-split-" + args.prec),
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "nb": args.nb,
                    "generator": inputs.WORKLOADS[args.workload][0],
                    "flop_model": "39 n^3 nominal"},
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "budget_s": args.budget_s,
         "time_s": ms_per_step / 1000.0,
         "gflops_executed": stats[-1]["flops"] / (ms_per_step * 1e-3) / 1e9,
         "ir": {k: stats[-1][k] for k in ("cols_extra_ir", "ir_steps", "ir_failures",
@@ -339,29 +442,48 @@ def main():
         "profiled_step": breakdown,
         "roofline": roof,
         "roofline_by_class": by_class,
+        "skipped": [],
     }
-    if not args.no_check:
+
+    def fits(name, est):
+        if name not in kept:
+            result["skipped"].append(name)
+            return False
+        if budget.left() < est + 5.0:
+            result["skipped"].append(name)
+            log("skipping %s: %.0f s estimated, %.0f s left" % (name, est, budget.left()))
+            return False
+        return True
+
+    est = dict(tail)
+    if not args.no_check and fits("check", est["check"]):
         inv = checks.invariants(A0d, B0d, A, B, Q, Z)
         result["backward_error"] = {k: inv[k] for k in ("bwd_A", "bwd_B", "orth_Q", "orth_Z",
                                                        "zeros_H", "zeros_T")}
         result["invariants_ok"] = bool(checks.invariants_ok(inv, n))
+        log("invariants checked")
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0 and \
+            fits("cpu_baseline", est["cpu_baseline"]):
+        log("cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline(A0, B0, args.cpu_seconds)
+        log("cpu baseline done")
     if not args.no_forms:
         result["forms"] = {}
-        if prec == htred.HT_PREC_FP64:
+        if fp64:
             for name in ("bf16", "fp8"):
-                print("bench: precision form %s ..." % name, file=sys.stderr, flush=True)
+                if not fits("precision_" + name, est["precision_" + name]):
+                    continue
+                log("precision form %s ..." % name)
                 result["forms"]["precision_" + name] = precision_form(
                     torch, htred, checks, A0d, B0d, A, B, Q, Z, ws, args.nb, name,
                     ms_per_step / 1000.0)
     del A0d, B0d, A, B, Q, Z, ws
     torch.cuda.empty_cache()
-    if not args.no_forms:
-        print("bench: batched form ...", file=sys.stderr, flush=True)
+    if not args.no_forms and fits("batched", est["batched"]):
+        log("batched form ...")
         result["forms"]["batched"] = batched_form(torch, htred, inputs, checks)
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
-        print("bench: cpu baseline ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(A0, B0, args.cpu_seconds)
+    result["wall_s"] = time.time() - T_START
     print(json.dumps(result), flush=True)
 
 

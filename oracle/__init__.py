@@ -11,4 +11,4 @@ The C part lives in ``ht_oracle.c``; ``build_oracle()`` compiles it with gcc
 into ``_build/liboracle.so``.  ``checks`` holds the comparison helpers (sign
 normalisation, invariants, a Krylov-basis reference for tiny n).
 """
-from .core import basic_ht, ms_ht, house, normal, build_oracle, oracle_lib_path  # noqa: F401
+from .core import basic_ht, ms_ht, fast_ht, fast_flops, house, normal, build_oracle, oracle_lib_path  # noqa: F401

@@ -21,13 +21,14 @@ def oracle_lib_path():
 
 
 def build_oracle(force=True):
-    """Compile ht_oracle.c with gcc (plain C, -O2, strict IEEE: no -ffast-math)."""
+    """Compile ht_oracle.c with gcc (plain C, -O2, strict IEEE: no -ffast-math;
+    OpenMP for the independent loops of the O(n^3) form)."""
     os.makedirs(_BUILD, exist_ok=True)
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-                           "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+                           "-ffp-contract=off", "-fopenmp", _SRC, "-o", tmp, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -46,6 +47,11 @@ def _load():
     lib.orc_basic_ht.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, ctypes.c_uint64]
     lib.orc_ms_ht.restype = None
     lib.orc_ms_ht.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
+    lib.orc_fast_ht.restype = ctypes.c_int
+    lib.orc_fast_ht.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, ctypes.c_uint64,
+                                ctypes.c_int, dp]
+    lib.orc_fast_flops.restype = ctypes.c_double
+    lib.orc_fast_flops.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.orc_normal.restype = ctypes.c_double
     lib.orc_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     _lib = lib
@@ -102,6 +108,40 @@ def ms_ht(A, B, ncols=None):
         ncols = max(n - 2, 0)
     lib.orc_ms_ht(n, _ptr(H), _ptr(T), _ptr(Q), _ptr(Z), int(ncols))
     return H, T, Q, Z
+
+
+def fast_ht(A, B, ncols=None, seed=0, threads=0, timing=None):
+    """O-fast: Algorithm 2's reflector pair per column with B kept triangular
+    by rank-one QR updates (Givens), Theta(n^3).  Returns (H, T, Q, Z,
+    n_perturbed).  ``threads`` OpenMP threads (0: the runtime default); the
+    result does not depend on it.  The C call releases the GIL, so several
+    pencils can be reduced from Python threads at once (threads=1 each).
+    If ``timing`` is a dict, timing["loop_s"] receives the wall time of the
+    column loop alone and timing["columns"] the columns reduced; a positive
+    timing["limit_s"] on entry stops the loop after the first column that
+    reaches that many seconds (a bounded sample of a large reduction)."""
+    lib = _load()
+    n = A.shape[0]
+    H, T = _fcopy(A), _fcopy(B)
+    Q = np.zeros((n, n), order="F")
+    Z = np.zeros((n, n), order="F")
+    if ncols is None:
+        ncols = max(n - 2, 0)
+    tm = (ctypes.c_double * 2)(float(timing.get("limit_s", 0.0)) if timing else 0.0, 0.0)
+    npert = lib.orc_fast_ht(n, _ptr(H), _ptr(T), _ptr(Q), _ptr(Z), int(ncols), int(seed),
+                            int(threads), tm)
+    if timing is not None:
+        timing["loop_s"] = tm[0]
+        timing["columns"] = int(tm[1])
+    return H, T, Q, Z, npert
+
+
+def fast_flops(n, ncols=None):
+    """Modelled flop count of fast_ht's first ``ncols`` columns (all by
+    default): about 33 n^3 for the whole reduction."""
+    if ncols is None:
+        ncols = max(n - 2, 0)
+    return _load().orc_fast_flops(int(n), int(ncols))
 
 
 def normal(seed, counter):

@@ -46,6 +46,10 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IDX(i, j, ld) ((size_t)(j) * (size_t)(ld) + (size_t)(i))
 
@@ -334,3 +338,383 @@ void orc_ms_ht(int n, double *A, double *B, double *Q, double *Z, int ncols)
 
 /* Frobenius norm exported for the Python side's tolerance computations. */
 double orc_frobenius(int n, const double *X) { return orc_frob(n, X); }
+
+/* ------------------------------------------------------------------------ */
+/* O-fast: Algorithm 2's reflector pair per column, with the trailing block */
+/* of B kept upper triangular, so every solve is a triangular one.          */
+/* ------------------------------------------------------------------------ */
+/*
+ * Per column j (m = n-j-1 trailing rows/columns, R = B(j+1:n, j+1:n) upper
+ * triangular on entry):
+ *   1. F = I - tau v v^T = House(A(j+1:n, j)) is applied to A(j+1:n, j:n)
+ *      and accumulated in Q(:, j+1:n), exactly as in Algorithm 2.
+ *   2. x solves (F R) x = e1, i.e. R x = F e1 = e1 - tau v v(1): the
+ *      right-hand side of the first-column formula of Sec. 2.2 / 3.2.2,
+ *      by scaled back substitution.
+ *   3. G = I - gamma w w^T = House(x) is applied to A(:, j+1:n),
+ *      Z(:, j+1:n) and the rows 0..j of B(:, j+1:n).
+ *   4. F R G = R - tau v t^T - gamma p w^T with t = R^T v and
+ *      p = R w - tau v (t^T w).  Its first column is a multiple of e1 up to
+ *      rounding (Lemma 2.1) and is set to that; its first row is formed
+ *      directly; its trailing block is R22 + a1 b1^T + a2 b2^T with
+ *      a1 = -tau v(2:m), b1 = t(2:m), a2 = -gamma p(2:m), b2 = w(2:m).
+ *   5. The trailing block is made triangular again by two rank-one QR
+ *      updates with Givens rotations (Golub & Van Loan, Matrix
+ *      Computations, Sec. 6.5): rotations bottom-up turn a into ||a|| e1
+ *      (R22 becomes upper Hessenberg), the rank-one term then only changes
+ *      the first row, and rotations top-down restore the triangle.  a2 is
+ *      rotated along with the first update.  These rotations act on rows
+ *      j+2..n-1 only; they are further left transformations, applied to
+ *      A(j+2:n, j+1:n) and accumulated in Q(:, j+2:n).  They leave the
+ *      reduced columns of A and column j+1 of B untouched, and Q e1 = e1.
+ * The result satisfies the same problem statement as Algorithm 2 (Q e1 =
+ * e1, H Hessenberg, T triangular), so by the implicit-Q theorem it equals
+ * Algorithm 2's up to the signs of the columns of Q and Z.  Cost
+ * Theta(n^3) (about 33 n^3 flops) instead of Theta(n^4).
+ *
+ * OpenMP parallelises only loops whose iterations are independent
+ * (columns of A and R, row chunks of Q and Z); every sum is formed in the
+ * same order whatever the thread count, so results are bitwise independent
+ * of it.
+ */
+
+typedef struct { int p; double c, s; } orc_rot;  /* rows (p, p+1): [c s; -s c] */
+
+static int orc_nthreads(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/* x(p), x(p+1) <- [c s; -s c] (x(p), x(p+1)) for rotations r[0..nr) in
+ * order, skipping those with p > pmax (they meet only zeros of x). */
+static void orc_rot_vec(const orc_rot *r, int nr, double *x, int pmax)
+{
+    for (int k = 0; k < nr; k++) {
+        const int p = r[k].p;
+        if (p > pmax) continue;
+        const double a = x[p], b = x[p + 1];
+        x[p] = r[k].c * a + r[k].s * b;
+        x[p + 1] = -r[k].s * a + r[k].c * b;
+    }
+}
+
+/* X(:, p), X(:, p+1) <- same rotation on columns, rows 0..nr-1: this is
+ * X <- X Omega^T for the left rotation Omega, i.e. the accumulation of Q. */
+static void orc_rot_cols_list(int nrows, double *X, int ld, const orc_rot *r, int nrot, int nt)
+{
+    const int CH = 64;
+    const int nch = (nrows + CH - 1) / CH;
+    #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && nrot > 16)
+    for (int ch = 0; ch < nch; ch++) {
+        const int r0 = ch * CH, r1 = r0 + CH < nrows ? r0 + CH : nrows;
+        for (int k = 0; k < nrot; k++) {
+            double *x0 = X + IDX(0, r[k].p, ld), *x1 = X + IDX(0, r[k].p + 1, ld);
+            const double c = r[k].c, s = r[k].s;
+            for (int i = r0; i < r1; i++) {
+                const double a = x0[i], b = x1[i];
+                x0[i] = c * a + s * b;
+                x1[i] = -s * a + c * b;
+            }
+        }
+    }
+}
+
+/* Rotations r[0..nr) in order to the columns c0..c1-1 (at most four) of X,
+ * interleaved so that the columns' independent dependency chains overlap.
+ * Each column gets exactly the arithmetic of orc_rot_vec. */
+static void orc_rot_group(const orc_rot *r, int nr, double *X, int ld, int c0, int c1)
+{
+    if (c1 - c0 < 4) {
+        for (int c = c0; c < c1; c++) orc_rot_vec(r, nr, X + IDX(0, c, ld), 1 << 30);
+        return;
+    }
+    double *x0 = X + IDX(0, c0, ld), *x1 = x0 + ld, *x2 = x1 + ld, *x3 = x2 + ld;
+    for (int k = 0; k < nr; k++) {
+        const int p = r[k].p;
+        const double c = r[k].c, s = r[k].s;
+        const double a0 = x0[p], b0 = x0[p + 1], a1 = x1[p], b1 = x1[p + 1];
+        const double a2 = x2[p], b2 = x2[p + 1], a3 = x3[p], b3 = x3[p + 1];
+        x0[p] = c * a0 + s * b0; x0[p + 1] = -s * a0 + c * b0;
+        x1[p] = c * a1 + s * b1; x1[p + 1] = -s * a1 + c * b1;
+        x2[p] = c * a2 + s * b2; x2[p + 1] = -s * a2 + c * b2;
+        x3[p] = c * a3 + s * b3; x3[p + 1] = -s * a3 + c * b3;
+    }
+}
+
+/* Columns c0..c1-1 of X (rows in the rotations' frame) <- rotations in
+ * order, in groups of four columns. */
+static void orc_rot_rows_list(int c0, int c1, double *X, int ld, const orc_rot *r, int nrot,
+                              int nt)
+{
+    const int ng = (c1 - c0 + 3) / 4;
+    #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && ng > 8)
+    for (int g = 0; g < ng; g++) {
+        const int a = c0 + 4 * g, b = a + 4 < c1 ? a + 4 : c1;
+        orc_rot_group(r, nrot, X, ld, a, b);
+    }
+}
+
+/* Rank-one QR update of the upper triangular R (m x m, ld): R + a b^T is
+ * brought back to upper triangular form by left rotations, which are
+ * appended to rot[] (first the bottom-up ones, then the top-down ones) and
+ * also applied to the vector `carry` (may be NULL).  a is destroyed.
+ * Returns the number of rotations written (2 (m-1) at most). */
+static int orc_qr_rank1(int m, double *R, int ld, double *a, const double *b, double *carry,
+                        orc_rot *rot, int nt)
+{
+    int nr = 0;
+    if (m <= 0) return 0;
+    /* bottom-up: rotations on (p, p+1), p = m-2..0, turn a into +-||a|| e1 */
+    for (int p = m - 2; p >= 0; p--) {
+        double c, s;
+        orc_givens(a[p], a[p + 1], &c, &s);
+        const double ap = a[p], aq = a[p + 1];
+        a[p] = c * ap + s * aq;
+        a[p + 1] = 0.0;
+        rot[nr].p = p; rot[nr].c = c; rot[nr].s = s;
+        nr++;
+    }
+    const int nb = nr;
+    /* R <- (rotations) R: column col meets rotations with p <= col; it
+     * gains one subdiagonal entry (upper Hessenberg) */
+    {
+        const int ng = (m + 3) / 4;
+        #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && m > 64)
+        for (int g = 0; g < ng; g++) {
+            /* rotations with p > col come first and meet only the zeros of
+             * column col below its diagonal, so a group of columns may
+             * start at the first rotation its last column needs */
+            const int a = 4 * g, b = a + 4 < m ? a + 4 : m;
+            const int k0 = (m - 2) - (b - 1) > 0 ? (m - 2) - (b - 1) : 0;
+            orc_rot_group(rot + k0, nb - k0, R, ld, a, b);
+        }
+    }
+    if (carry) orc_rot_vec(rot, nb, carry, 1 << 30);
+    /* the rank-one term now lives in the first row */
+    for (int col = 0; col < m; col++) R[IDX(0, col, ld)] += a[0] * b[col];
+    /* top-down: rotation p zeroes the subdiagonal entry (p+1, p).  Columns
+     * are processed in blocks: inside a block serially (each rotation needs
+     * its column updated by the previous ones), then the block's rotations
+     * go to all later columns at once. */
+    const int NBK = 64;
+    orc_rot *td = rot + nr;
+    for (int c0 = 0; c0 < m - 1; c0 += NBK) {
+        const int c1 = c0 + NBK < m - 1 ? c0 + NBK : m - 1;
+        for (int col = c0; col < c1; col++) {
+            double *x = R + IDX(0, col, ld);
+            orc_rot_vec(td + c0, col - c0, x, 1 << 30);
+            double c, s;
+            orc_givens(x[col], x[col + 1], &c, &s);
+            const double xp = x[col], xq = x[col + 1];
+            x[col] = c * xp + s * xq;
+            x[col + 1] = 0.0;
+            td[col].p = col; td[col].c = c; td[col].s = s;
+        }
+        orc_rot_rows_list(c1, m, R, ld, td + c0, c1 - c0, nt);
+    }
+    nr += m - 1;
+    if (carry) orc_rot_vec(td, m - 1, carry, 1 << 30);
+    return nr;
+}
+
+/* Upper triangular R (m x m, ld): x = sigma R^{-1} y with 0 < sigma <= 1,
+ * column-oriented back substitution that shrinks the partial solution and
+ * the remaining right-hand side by 2^-600 whenever the next entry would
+ * exceed 2^600 (only the direction of x is used, Lemma 2.1).  y is
+ * overwritten. */
+static void orc_trsv_scaled(int m, const double *R, int ld, double *y, double *x)
+{
+    const double big = 0x1.0p600, shrink = 0x1.0p-600;
+    for (int i = m - 1; i >= 0; i--) {
+        const double d = R[IDX(i, i, ld)];
+        while (fabs(y[i]) > big * fabs(d) || fabs(y[i]) > big) {
+            for (int t = 0; t <= i; t++) y[t] *= shrink;
+            for (int t = i + 1; t < m; t++) x[t] *= shrink;
+        }
+        x[i] = y[i] / d;
+        const double *col = R + IDX(0, i, ld);
+        for (int r = 0; r < i; r++) y[r] -= col[r] * x[i];
+    }
+}
+
+/* Modelled flops of column j of orc_fast_ht (the loops below counted as
+ * 2 per multiply-add, 6 per rotation and entry). */
+static double orc_fast_col_flops(int n, int j)
+{
+    const double m = n - j - 1, m2 = m - 1, N = n;
+    return 4 * m * m + 4 * N * m          /* F to A, Q */
+         + m * m + m * m                  /* t = R^T v, solve */
+         + 8 * N * m + 4 * (j + 1.0) * m  /* G to A, Z, B rows 0..j */
+         + m * m                          /* p = R w */
+         + 12 * m2 * m2                   /* two rank-one QR updates of R22 */
+         + 24 * m2 * m + 24 * m2 * N;     /* their rotations to A and Q */
+}
+
+double orc_fast_flops(int n, int ncols)
+{
+    double f = 0.0;
+    if (ncols > n - 2) ncols = n - 2;
+    for (int j = 0; j < ncols; j++) f += orc_fast_col_flops(n, j);
+    return f;
+}
+
+/* X(0:nr, 0:m) <- X (I - beta v v^T), rows in parallel chunks (each row's
+ * sum in the same order as orc_apply_right). */
+static void orc_apply_right_par(int nr, int m, const double *v, double beta, double *X, int ldx,
+                                int nt)
+{
+    if (beta == 0.0 || nr <= 0 || m <= 0) return;
+    const int CH = 64;
+    const int nch = (nr + CH - 1) / CH;
+    #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && nch > 1)
+    for (int ch = 0; ch < nch; ch++) {
+        const int r0 = ch * CH, r1 = r0 + CH < nr ? r0 + CH : nr;
+        double acc[64];
+        for (int r = r0; r < r1; r++) acc[r - r0] = 0.0;
+        for (int c = 0; c < m; c++) {
+            const double *col = X + IDX(0, c, ldx);
+            for (int r = r0; r < r1; r++) acc[r - r0] += col[r] * v[c];
+        }
+        for (int c = 0; c < m; c++) {
+            double *col = X + IDX(0, c, ldx);
+            const double f = beta * v[c];
+            for (int r = r0; r < r1; r++) col[r] -= acc[r - r0] * f;
+        }
+    }
+}
+
+/* Reduces the first `ncols` columns (pass n-2 for the full reduction) with
+ * `nthreads` OpenMP threads (0: the runtime's default).  A, B are
+ * overwritten by H, T; Q, Z are set.  B must be upper triangular on entry
+ * (its strictly lower triangle is ignored and set to zero).  Returns the
+ * number of zero pivots replaced by 2 u rho ||B||_F.  `timing` may be
+ * NULL, or point to 2 doubles: on entry timing[0] > 0 limits the column
+ * loop to that many seconds (it stops after the first column that reaches
+ * the limit); on exit timing[0] is the wall time of the column loop alone
+ * (without the set-up of Q, Z and ||B||_F) and timing[1] the number of
+ * columns reduced. */
+int orc_fast_ht(int n, double *A, double *B, double *Q, double *Z, int ncols, uint64_t seed,
+                int nthreads, double *timing)
+{
+    const double u = 0x1.0p-53;
+    const int nt = orc_nthreads(nthreads);
+    orc_identity(n, Q);
+    orc_identity(n, Z);
+    for (int c = 0; c < n; c++)
+        for (int i = c + 1; i < n; i++) B[IDX(i, c, n)] = 0.0;
+    if (ncols > n - 2) ncols = n - 2;
+    const double normB = orc_frob(n, B);
+    uint64_t draws = 0;
+    int perturbed = 0;
+    const size_t N = n > 0 ? (size_t)n : 1;
+    double *v = (double *)malloc(N * sizeof(double));
+    double *w = (double *)malloc(N * sizeof(double));
+    double *t = (double *)malloc(N * sizeof(double));
+    double *p = (double *)malloc(N * sizeof(double));
+    double *y = (double *)malloc(N * sizeof(double));
+    double *x = (double *)malloc(N * sizeof(double));
+    double *a1 = (double *)malloc(N * sizeof(double));
+    double *a2 = (double *)malloc(N * sizeof(double));
+    orc_rot *rot = (orc_rot *)malloc(4 * N * sizeof(orc_rot));
+
+    const double limit = timing && timing[0] > 0.0 ? timing[0] : 0.0;
+    struct timespec ts0, ts1;
+    clock_gettime(CLOCK_MONOTONIC, &ts0);
+    int done = 0;
+    for (int j = 0; j < ncols; j++) {
+        const int o = j + 1, m = n - j - 1;
+        double *R = B + IDX(o, o, n);
+        /* 1. left reflector F on A(j+1:n, j:n), accumulated in Q */
+        double tau;
+        const double alpha = orc_house(m, A + IDX(o, j, n), v, &tau);
+        if (tau != 0.0) {
+            #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && m > 64)
+            for (int c = j + 1; c < n; c++) {
+                double *col = A + IDX(o, c, n);
+                double d = 0.0;
+                for (int i = 0; i < m; i++) d += v[i] * col[i];
+                d *= tau;
+                for (int i = 0; i < m; i++) col[i] -= d * v[i];
+            }
+        }
+        A[IDX(o, j, n)] = alpha;
+        for (int i = o + 1; i < n; i++) A[IDX(i, j, n)] = 0.0;
+        orc_apply_right_par(n, m, v, tau, Q + IDX(0, o, n), n, nt);
+        /* t = R^T v */
+        #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && m > 64)
+        for (int c = 0; c < m; c++) {
+            const double *col = R + IDX(0, c, n);
+            double d = 0.0;
+            for (int i = 0; i <= c; i++) d += col[i] * v[i];
+            t[c] = d;
+        }
+        /* 2. x = sigma R^{-1} (e1 - tau v v(1)); zero pivots first */
+        for (int i = 0; i < m; i++)
+            if (R[IDX(i, i, n)] == 0.0) {
+                R[IDX(i, i, n)] = 2.0 * u * orc_normal(seed, draws++) * normB;
+                perturbed++;
+            }
+        for (int i = 0; i < m; i++) y[i] = -tau * v[i] * v[0];
+        y[0] += 1.0;
+        orc_trsv_scaled(m, R, n, y, x);
+        /* 3. right reflector G = House(x) on A(:, j+1:n), Z, B(0:j+1, j+1:n) */
+        double gamma;
+        orc_house(m, x, w, &gamma);
+        orc_apply_right_par(n, m, w, gamma, A + IDX(0, o, n), n, nt);
+        orc_apply_right_par(n, m, w, gamma, Z + IDX(0, o, n), n, nt);
+        orc_apply_right_par(o, m, w, gamma, B + IDX(0, o, n), n, nt);
+        /* 4. F R G = R - tau v t^T - gamma p w^T, p = R w - tau v (t^T w) */
+        double tw = 0.0;
+        for (int i = 0; i < m; i++) tw += t[i] * w[i];
+        {
+            const int CH = 64, nch = (m + CH - 1) / CH;
+            #pragma omp parallel for num_threads(nt) schedule(static) if (nt > 1 && m > 256)
+            for (int ch = 0; ch < nch; ch++) {
+                const int r0 = ch * CH, r1 = r0 + CH < m ? r0 + CH : m;
+                for (int i = r0; i < r1; i++) p[i] = 0.0;
+                for (int c = r0; c < m; c++) {
+                    const double *col = R + IDX(0, c, n);
+                    const int re = c + 1 < r1 ? c + 1 : r1;
+                    for (int i = r0; i < re; i++) p[i] += col[i] * w[c];
+                }
+                for (int i = r0; i < r1; i++) p[i] -= tau * v[i] * tw;
+            }
+        }
+        for (int c = 0; c < m; c++)
+            R[IDX(0, c, n)] += -tau * v[0] * t[c] - gamma * p[0] * w[c];
+        for (int i = 1; i < m; i++) R[IDX(i, 0, n)] = 0.0;
+        /* 5. trailing block R22 + a1 t(2:m)^T + a2 w(2:m)^T back to triangular */
+        const int m2 = m - 1;
+        if (m2 >= 1) {
+            double *R22 = R + IDX(1, 1, n);
+            for (int i = 0; i < m2; i++) {
+                a1[i] = -tau * v[i + 1];
+                a2[i] = -gamma * p[i + 1];
+            }
+            int nr = orc_qr_rank1(m2, R22, n, a1, t + 1, a2, rot, nt);
+            nr += orc_qr_rank1(m2, R22, n, a2, w + 1, NULL, rot + nr, nt);
+            /* the rotations (rows j+2..n-1) on A(j+2:n, j+1:n) and Q(:, j+2:n) */
+            orc_rot_rows_list(0, m, A + IDX(o + 1, o, n), n, rot, nr, nt);
+            orc_rot_cols_list(n, Q + IDX(0, o + 1, n), n, rot, nr, nt);
+        }
+        done = j + 1;
+        if (limit > 0.0) {
+            clock_gettime(CLOCK_MONOTONIC, &ts1);
+            if ((double)(ts1.tv_sec - ts0.tv_sec) + 1e-9 * (double)(ts1.tv_nsec - ts0.tv_nsec) >= limit)
+                break;
+        }
+    }
+    clock_gettime(CLOCK_MONOTONIC, &ts1);
+    if (timing) {
+        timing[0] = (double)(ts1.tv_sec - ts0.tv_sec) + 1e-9 * (double)(ts1.tv_nsec - ts0.tv_nsec);
+        timing[1] = (double)done;
+    }
+    free(v); free(w); free(t); free(p); free(y); free(x);
+    free(a1); free(a2); free(rot);
+    return perturbed;
+}

@@ -32,26 +32,33 @@ Named workloads (``workload(name)``):
 import numpy as np
 
 
-def random_pencil(n, seed):
+def _layout(M, order):
+    return np.asfortranarray(M) if order == "F" else np.ascontiguousarray(M)
+
+
+def random_pencil(n, seed, order="F"):
+    """``order`` only picks the memory layout of the returned arrays ("F":
+    column-major, "C": row-major, which skips a large transposing copy);
+    the matrices are the same."""
     rng = np.random.default_rng(seed)
-    A = np.asfortranarray(rng.standard_normal((n, n)))
+    A = _layout(rng.standard_normal((n, n)), order)
     G = rng.standard_normal((n, n))
     if n == 0:
-        return A, np.asfortranarray(G)
+        return A, _layout(G, order)
     R = np.linalg.qr(G, mode="r")
-    B = np.asfortranarray(np.triu(R))
+    B = _layout(np.triu(R), order)
     return A, B
 
 
-def illcond_pencil(n, seed):
+def illcond_pencil(n, seed, order="F"):
     rng = np.random.default_rng(seed)
-    A = np.asfortranarray(rng.standard_normal((n, n)))
+    A = _layout(rng.standard_normal((n, n)), order)
     B = rng.standard_normal((n, n))
     B = np.triu(B, 1)
     mags = 10.0 ** rng.uniform(-8.0, 0.0, size=n)
     signs = np.where(rng.integers(0, 2, size=n) == 0, -1.0, 1.0)
     B[np.arange(n), np.arange(n)] = signs * mags
-    return A, np.asfortranarray(B)
+    return A, _layout(B, order)
 
 
 def saddle_pencil(n, seed):
@@ -93,9 +100,9 @@ WORKLOADS = {
 }
 
 
-def workload(name, n=None):
+def workload(name, n=None, order="F"):
     kind, n0, seed = WORKLOADS[name]
     n = n0 if n is None else n
     if kind == "random":
-        return random_pencil(n, seed)
-    return illcond_pencil(n, seed)
+        return random_pencil(n, seed, order)
+    return illcond_pencil(n, seed, order)
