@@ -33,13 +33,28 @@ def build_oracle(force=True):
     return _LIB
 
 
+def build_planted_variant(out_dir, plant):
+    """Compile a copy of the oracle with the deliberate mistake number
+    `plant` (ORC_PLANT in ht_oracle.c) into out_dir and load it; used only
+    by the tests that show the pins catch such mistakes."""
+    path = os.path.join(str(out_dir), "liboracle_plant%d.so" % int(plant))
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-fopenmp", "-DORC_PLANT=%d" % int(plant), _SRC,
+                           "-o", path, "-lm"])
+    return _bind(ctypes.CDLL(path))
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         build_oracle()
-    lib = ctypes.CDLL(_LIB)
+    _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _bind(lib):
     dp = ctypes.POINTER(ctypes.c_double)
     lib.orc_house.restype = ctypes.c_double
     lib.orc_house.argtypes = [ctypes.c_int, dp, dp, dp]
@@ -54,7 +69,6 @@ def _load():
     lib.orc_fast_flops.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.orc_normal.restype = ctypes.c_double
     lib.orc_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
-    _lib = lib
     return lib
 
 
@@ -110,7 +124,7 @@ def ms_ht(A, B, ncols=None):
     return H, T, Q, Z
 
 
-def fast_ht(A, B, ncols=None, seed=0, threads=0, timing=None):
+def fast_ht(A, B, ncols=None, seed=0, threads=0, timing=None, lib=None):
     """O-fast: Algorithm 2's reflector pair per column with B kept triangular
     by rank-one QR updates (Givens), Theta(n^3).  Returns (H, T, Q, Z,
     n_perturbed).  ``threads`` OpenMP threads (0: the runtime default); the
@@ -119,8 +133,9 @@ def fast_ht(A, B, ncols=None, seed=0, threads=0, timing=None):
     If ``timing`` is a dict, timing["loop_s"] receives the wall time of the
     column loop alone and timing["columns"] the columns reduced; a positive
     timing["limit_s"] on entry stops the loop after the first column that
-    reaches that many seconds (a bounded sample of a large reduction)."""
-    lib = _load()
+    reaches that many seconds (a bounded sample of a large reduction).
+    ``lib`` selects another build of the oracle (build_planted_variant)."""
+    lib = lib or _load()
     n = A.shape[0]
     H, T = _fcopy(A), _fcopy(B)
     Q = np.zeros((n, n), order="F")

@@ -380,6 +380,18 @@ double orc_frobenius(int n, const double *X) { return orc_frob(n, X); }
 
 typedef struct { int p; double c, s; } orc_rot;  /* rows (p, p+1): [c s; -s c] */
 
+/* ORC_PLANT (compile-time, default 0) plants one deliberate mistake in the
+ * O(n^3) form so that the tests can show their pins catch it; the library
+ * the tests and benchmarks use is always built with 0.
+ *   1: a2 is not rotated along with the first rank-one update;
+ *   2: p = R w, dropping the -tau v (t^T w) term of F R G;
+ *   3: the rotations are not accumulated in Q;
+ *   4: the solve uses e1 instead of F e1 as its right-hand side;
+ *   5: Q accumulates Omega instead of Omega^T (a transposed rotation). */
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
+
 static int orc_nthreads(int nthreads)
 {
 #ifdef _OPENMP
@@ -414,7 +426,7 @@ static void orc_rot_cols_list(int nrows, double *X, int ld, const orc_rot *r, in
         const int r0 = ch * CH, r1 = r0 + CH < nrows ? r0 + CH : nrows;
         for (int k = 0; k < nrot; k++) {
             double *x0 = X + IDX(0, r[k].p, ld), *x1 = X + IDX(0, r[k].p + 1, ld);
-            const double c = r[k].c, s = r[k].s;
+            const double c = r[k].c, s = ORC_PLANT == 5 ? -r[k].s : r[k].s;
             for (int i = r0; i < r1; i++) {
                 const double a = x0[i], b = x1[i];
                 x0[i] = c * a + s * b;
@@ -659,7 +671,7 @@ int orc_fast_ht(int n, double *A, double *B, double *Q, double *Z, int ncols, ui
                 R[IDX(i, i, n)] = 2.0 * u * orc_normal(seed, draws++) * normB;
                 perturbed++;
             }
-        for (int i = 0; i < m; i++) y[i] = -tau * v[i] * v[0];
+        for (int i = 0; i < m; i++) y[i] = ORC_PLANT == 4 ? 0.0 : -tau * v[i] * v[0];
         y[0] += 1.0;
         orc_trsv_scaled(m, R, n, y, x);
         /* 3. right reflector G = House(x) on A(:, j+1:n), Z, B(0:j+1, j+1:n) */
@@ -682,7 +694,8 @@ int orc_fast_ht(int n, double *A, double *B, double *Q, double *Z, int ncols, ui
                     const int re = c + 1 < r1 ? c + 1 : r1;
                     for (int i = r0; i < re; i++) p[i] += col[i] * w[c];
                 }
-                for (int i = r0; i < r1; i++) p[i] -= tau * v[i] * tw;
+                if (ORC_PLANT != 2)
+                    for (int i = r0; i < r1; i++) p[i] -= tau * v[i] * tw;
             }
         }
         for (int c = 0; c < m; c++)
@@ -696,11 +709,11 @@ int orc_fast_ht(int n, double *A, double *B, double *Q, double *Z, int ncols, ui
                 a1[i] = -tau * v[i + 1];
                 a2[i] = -gamma * p[i + 1];
             }
-            int nr = orc_qr_rank1(m2, R22, n, a1, t + 1, a2, rot, nt);
+            int nr = orc_qr_rank1(m2, R22, n, a1, t + 1, ORC_PLANT == 1 ? NULL : a2, rot, nt);
             nr += orc_qr_rank1(m2, R22, n, a2, w + 1, NULL, rot + nr, nt);
             /* the rotations (rows j+2..n-1) on A(j+2:n, j+1:n) and Q(:, j+2:n) */
             orc_rot_rows_list(0, m, A + IDX(o + 1, o, n), n, rot, nr, nt);
-            orc_rot_cols_list(n, Q + IDX(0, o + 1, n), n, rot, nr, nt);
+            if (ORC_PLANT != 3) orc_rot_cols_list(n, Q + IDX(0, o + 1, n), n, rot, nr, nt);
         }
         done = j + 1;
         if (limit > 0.0) {

@@ -277,3 +277,158 @@ def test_saddle_point_pencils(n):
     assert np.count_nonzero(np.diag(B) == 0.0) == n - (3 * n) // 4
     _check_inv(A, B, oracle.basic_ht(A, B))
     _check_inv(A, B, oracle.ms_ht(A, B))
+
+
+# ------------------------------------------------ O-fast, the O(n^3) form ---
+# Algorithm 2's reflector pair per column with B kept triangular by Givens
+# rank-one QR updates.  Pinned against Algorithm 2 itself and against
+# Moler-Stewart (a different algorithm: the implicit-Q theorem makes the
+# sign-normalised outputs agree), the Krylov characterisation, scipy's
+# Hessenberg form for B = I, the golden 3 x 3 case, the invariants of
+# Theorem A.1, and planted mistakes that each pin must catch.
+
+@pytest.mark.parametrize("n", [3, 4, 5, 8, 16, 64, 128, 256])
+def test_fast_matches_algorithm2_and_moler_stewart(n):
+    A, B = inputs.random_pencil(n, seed=500 + n)
+    got = oracle.fast_ht(A, B)
+    _check_inv(A, B, got)
+    refs = [oracle.ms_ht(A, B)]
+    if n <= 128:
+        refs.append(oracle.basic_ht(A, B)[:4])
+    for ref in refs:
+        d = checks.compare(ref, got[:4], A, B)
+        for key in ("max_H", "max_T", "max_Q", "max_Z"):
+            assert d[key] < 1e-12, (n, key, d)
+
+
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_fast_matches_krylov_characterisation(n):
+    A, B = inputs.random_pencil(n, seed=600 + n)
+    d = checks.compare(checks.krylov_reference(A, B), oracle.fast_ht(A, B)[:4], A, B)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-9, (key, d)
+
+
+def test_fast_identity_B_gives_hessenberg_form():
+    n = 40
+    rng = np.random.default_rng(41)
+    A = np.asfortranarray(rng.standard_normal((n, n)))
+    H, T, Q, Z, _ = oracle.fast_ht(A, np.eye(n, order="F"))
+    Hs, Qs = sl.hessenberg(A, calc_q=True)
+    d = checks.compare((Hs, np.eye(n), Qs, Qs), (H, T, Q, Z), A, np.eye(n))
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-12, (key, d)
+
+
+def test_fast_golden_3x3_and_tiny_orders():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "hessenberg_3x3_identity_B.json")
+    with open(path) as f:
+        g = json.load(f)
+    A = np.asfortranarray(np.array(g["A"], dtype=np.float64))
+    B = np.asfortranarray(np.array(g["B"], dtype=np.float64))
+    ref = tuple(np.array(g[k], dtype=np.float64) for k in ("H", "T", "Q", "Z"))
+    d = checks.compare(ref, oracle.fast_ht(A, B)[:4], A, B)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-15, (key, d)
+    for n in (0, 1, 2):
+        A, B = inputs.random_pencil(n, seed=1)
+        H, T, Q, Z, _ = oracle.fast_ht(A, B)
+        assert np.array_equal(H, A) and np.array_equal(T, B)
+        assert np.array_equal(Q, np.eye(n)) and np.array_equal(Z, np.eye(n))
+
+
+def test_fast_is_independent_of_thread_count():
+    A, B = inputs.random_pencil(300, seed=7)
+    one = oracle.fast_ht(A, B, threads=1)
+    many = oracle.fast_ht(A, B, threads=4)
+    for a, b in zip(one[:4], many[:4]):
+        assert np.array_equal(a, b)
+
+
+def test_fast_partial_prefix_is_final():
+    """After c columns, H[:, :c], T[:, :c+1], Q[:, :c+1] and Z[:, :c+1] are
+    final; they match Moler-Stewart's prefix and the full O-fast run."""
+    n, c = 50, 11
+    A, B = inputs.random_pencil(n, seed=8)
+    full = oracle.fast_ht(A, B)[:4]
+    tm = {}
+    part = oracle.fast_ht(A, B, ncols=c, timing=tm)[:4]
+    assert tm["columns"] == c and tm["loop_s"] >= 0.0
+    assert np.array_equal(full[0][:, :c], part[0][:, :c])
+    assert np.array_equal(full[1][:, :c + 1], part[1][:, :c + 1])
+    assert np.array_equal(full[2][:, :c + 1], part[2][:, :c + 1])
+    assert np.array_equal(full[3][:, :c + 1], part[3][:, :c + 1])
+    d = checks.compare(oracle.ms_ht(A, B, ncols=c), part, A, B, upto=c)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] < 1e-12, (key, d)
+    # a time limit stops the loop after the first column that reaches it
+    tm = {"limit_s": 1e-9}
+    oracle.fast_ht(A, B, timing=tm)
+    assert tm["columns"] == 1
+
+
+@pytest.mark.parametrize("n", [32, 64, 160, 400])
+def test_fast_illconditioned_generator_stays_finite(n):
+    """The ill-conditioned generator of the n = 16384 workload makes B
+    numerically singular already at n = 16 (condition numbers 1e20..1e28),
+    so T is not numerically unique and Algorithm 2, Moler-Stewart and
+    O-fast disagree entry-wise; the invariants decide."""
+    A, B = inputs.illcond_pencil(n, seed=2)
+    out = oracle.fast_ht(A, B)
+    assert all(np.isfinite(M).all() for M in out[:4])
+    _check_inv(A, B, out)
+
+
+@pytest.mark.parametrize("kind", ["zero_diag", "saddle"])
+def test_fast_singular_B_stays_backward_stable(kind):
+    n = 32
+    if kind == "saddle":
+        A, B = inputs.saddle_pencil(n, seed=5)
+    else:
+        A, B = inputs.random_pencil(n, seed=77)
+        B = B.copy(order="F")
+        B[4, 4] = 0.0
+        B[17, 17] = 0.0
+    H, T, Q, Z, nper = oracle.fast_ht(A, B, seed=11)
+    assert nper > 0
+    _check_inv(A, B, (H, T, Q, Z))
+
+
+def test_fast_eigenvalues_preserved():
+    from scipy.optimize import linear_sum_assignment
+    n = 24
+    A, B = inputs.random_pencil(n, seed=424)
+    H, T, Q, Z, _ = oracle.fast_ht(A, B)
+    ev_ref = sl.eigvals(A, B)
+    ev_got = sl.eigvals(H, T)
+    dist = np.abs(ev_ref[:, None] - ev_got[None, :])
+    r, c = linear_sum_assignment(dist)
+    assert dist[r, c].max() <= 1e-8 * max(1.0, np.abs(ev_ref).max())
+
+
+@pytest.mark.parametrize("plant", [1, 2, 3, 4, 5])
+def test_fast_planted_mistakes_are_caught(tmp_path, plant):
+    """Each deliberate slip compiled into a copy of the oracle (a vector not
+    rotated, a dropped term, a missing or transposed accumulation, a wrong
+    right-hand side) fails the pins: the invariants or the sign-normalised
+    comparison with Moler-Stewart."""
+    from oracle import core
+    lib = core.build_planted_variant(tmp_path, plant)
+    n = 24
+    A, B = inputs.random_pencil(n, seed=2424)
+    got = oracle.fast_ht(A, B, lib=lib)[:4]
+    inv = checks.invariants(A, B, *got)
+    d = checks.compare(oracle.ms_ht(A, B), got, A, B)
+    worst = max(d["max_H"], d["max_T"], d["max_Q"], d["max_Z"])
+    assert (not checks.invariants_ok(inv, n)) and worst > 1e-6, (plant, inv, d)
+
+
+def test_fast_flop_model():
+    """The modelled work is Theta(n^3) with about 33 n^3 flops in all."""
+    f = oracle.fast_flops(2048)
+    assert 30.0 * 2048 ** 3 < f < 36.0 * 2048 ** 3
+    assert oracle.fast_flops(2048, 10) < f
+    assert oracle.fast_flops(2) == 0.0
