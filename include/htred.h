@@ -89,11 +89,18 @@ typedef struct {
     int32_t batch_wg_per_cu; /* ht_reduce_batched: resident workgroups per
                                 compute unit (each reduces one pencil at a
                                 time); 0 = default 3.  Must be 1..3. */
+    int32_t ilo;             /* ht_reduce: first column to reduce (0-based),
+                                default 0.  Columns 0..ilo-1 must already be in
+                                final form: A(i, j) = 0 for i > j + 1 and for
+                                i > ilo when j < ilo (B upper triangular as
+                                always), as after ht_preprocess.  Only columns
+                                ilo..n-3 are reduced; the transformations act on
+                                rows / columns ilo+1..n-1, on every row of A and
+                                B above them and on all of Q and Z. */
 } ht_options;
 
 /* flags */
-#define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs;
-                                   allocates a 4-byte device flag) */
+#define HT_FLAG_CHECK_FINITE 1  /* scan A, B for NaN/Inf on entry (syncs) */
 #define HT_FLAG_PROFILE      2  /* time kernel classes with HIP events (stats) */
 #define HT_FLAG_SOLVE_SOLO   4  /* triangular solves on one workgroup, without
                                    helper workgroups (slower; for testing) */
@@ -154,16 +161,74 @@ size_t ht_workspace_size(int64_t n, const ht_options *opt);
  *         256-byte aligned, owned by the caller.
  *   stream hipStream_t (void*), NULL = default stream.
  *
+ * Q and Z: with HT_QZ_IDENTITY they are set to I first (the problem
+ * statement's Q e1 = Z e1 = e1); with HT_QZ_ACCUMULATE the caller's Q_in and
+ * Z_in are multiplied from the right (Q <- Q_in Q, Z <- Z_in Z: every update
+ * of Q and Z in Sec. 3.3 is a right multiplication over all n rows), so a
+ * preceding orthogonal transformation (e.g. the QR factorisation that made
+ * B triangular) is carried along; with HT_QZ_NONE they are not touched.
+ * Leading dimensions must also be <= INT32_MAX (-6..-9 otherwise).
+ *
  * The call synchronises `stream` once per reflector pair and once per
- * iterative-refinement step to read the refinement verdict (through a
- * 256-byte pinned host buffer that the first call allocates once), so it
- * is not graph-capturable; ht_reduce_batched is.
+ * iterative-refinement step to read the refinement verdict, through a
+ * 256-byte pinned host buffer that the call allocates and frees itself, so
+ * it is not graph-capturable (ht_reduce_batched is).  The call keeps no
+ * state between calls: concurrent calls from several host threads on
+ * different streams (with different workspaces) are independent.
+ * HT_FLAG_CHECK_FINITE uses a word at the end of the caller's workspace, or
+ * a 4-byte device allocation when the library allocates.
  * Results are deterministic: no floating-point atomics are used.
  */
 int ht_reduce(double *A, double *B, double *Q, double *Z, int64_t n,
               int64_t lda, int64_t ldb, int64_t ldq, int64_t ldz,
               const ht_options *opt, ht_stats *stats,
               void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * ht_triangularize_b -- the first step of the QZ algorithm (Sec. 1): an
+ * orthogonal Q0 with B = Q0 R, R upper triangular, applied to the pencil:
+ *   B (in/out)  n x n general matrix on entry, R on exit (exact zeros below
+ *               the diagonal);
+ *   A (in/out)  n x n, replaced by Q0^T A;
+ *   Q           Q0 (qmode HT_QZ_IDENTITY), Q_in Q0 (HT_QZ_ACCUMULATE) or
+ *               untouched (HT_QZ_NONE, Q may be NULL).
+ * The pencil is then ready for ht_reduce with qmode HT_QZ_ACCUMULATE.  The
+ * QR factorisation runs in panels of opt->nb columns, each factored by the
+ * window chain of Sec. 3.3.2 b (the chain that triangularises U2) and
+ * applied by the same block-reflector sweeps as the absorption.  FP64 only
+ * (HT_ERR_UNSUPPORTED for a split precision); zmode is ignored.  workspace /
+ * ws_bytes as for ht_reduce (ht_workspace_size bytes for the same options,
+ * or NULL to let the library allocate).  Asynchronous on `stream` unless the
+ * library allocates (then it waits before freeing).  Returns -1..-3 for a
+ * NULL A, B or Q (Q only when formed), -5 for n outside 0..2^30, -6 / -7 /
+ * -8 for bad lda / ldb / ldq, -10 for invalid options.
+ */
+int ht_triangularize_b(double *A, double *B, double *Q, int64_t n, int64_t lda,
+                       int64_t ldb, int64_t ldq, const ht_options *opt,
+                       void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * ht_preprocess -- the zero-column preprocessing of Sec. 3.5: when the upper
+ * triangular B has l > 1 zero columns, a permutation Z0 moves them to the
+ * front (Q0 = Z0 when B is diagonal, so that it stays diagonal, else
+ * Q0 = I), the QR factorisation of the first l columns of Q0^T A Z0 gives
+ * Q1 with
+ *     (Q0 Q1)^T A Z0 = [A11 A12; 0 A22],   (Q0 Q1)^T B Z0 = [0 B12; 0 B22],
+ * A11 upper triangular, and B22 is made upper triangular again by the QR of
+ * ht_triangularize_b (Q2), applied to A22.  On exit A and B hold the new
+ * pencil, Q = Q0 Q1 diag(I, Q2) and Z = Z0 (times Q_in / Z_in with
+ * HT_QZ_ACCUMULATE), and *ilo = l: the leading l x l part is in generalised
+ * Schur form (l infinite eigenvalues) and ht_reduce with opt->ilo = l and
+ * qmode = zmode = HT_QZ_ACCUMULATE finishes the reduction of the whole
+ * pencil.  With fewer than two zero columns nothing is changed (Q, Z set
+ * per their modes) and *ilo = 0.  Allocates an n x n temporary and reads
+ * the zero-column pattern back to the host (waits for `stream`).  FP64
+ * only.  Returns as ht_triangularize_b, plus -4 / -9 for a NULL Z or bad
+ * ldz and -11 for a NULL ilo.
+ */
+int ht_preprocess(double *A, double *B, double *Q, double *Z, int64_t n, int64_t lda,
+                  int64_t ldb, int64_t ldq, int64_t ldz, const ht_options *opt,
+                  int32_t *ilo, void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * ht_reduce_batched -- independent HT reductions of `batch` small pencils in

@@ -102,6 +102,45 @@ def compare(ref, got, A0, B0, upto=None):
     return out
 
 
+def sign_normalise_ilo(H, T, Q, Z, ell):
+    """Sign normalisation of a reduction whose first `ell` columns were
+    fixed by the zero-column preprocessing (Z's first ell columns are
+    permutation columns, so d_z = +1 there; Q's come from a QR
+    factorisation, fixed by diag(H) >= 0 there).  Column ell starts the
+    trailing reduction: d_z = +1 (Z e_ell is a permutation column too) and
+    d_q from T(ell, ell) >= 0; from there on the rule of sign_vectors.
+    Numpy arrays only; returns (H', T', Q', Z')."""
+    n = H.shape[0]
+    dq = np.ones(n)
+    dz = np.ones(n)
+    for i in range(min(ell, n)):
+        dq[i] = _sgn(H[i, i])
+    if ell < n:
+        dq[ell] = _sgn(T[ell, ell])
+        for i in range(ell, n):
+            dz[i] = dq[i] * _sgn(T[i, i])
+            if i + 1 < n:
+                dq[i + 1] = dz[i] * _sgn(H[i + 1, i])
+    return dq[:, None] * H * dz[None, :], dq[:, None] * T * dz[None, :], Q * dq[None, :], \
+        Z * dz[None, :]
+
+
+def compare_ilo(ref, got, A0, B0, ell):
+    """compare() for reductions that start after `ell` preprocessed columns
+    (sign_normalise_ilo instead of sign_normalise)."""
+    n = A0.shape[0]
+    r = sign_normalise_ilo(*ref, ell)
+    g = sign_normalise_ilo(*got, ell)
+    nA, nB, sq = _fro(A0), _fro(B0), float(np.sqrt(max(n, 1)))
+    out = {}
+    for name, a, b, scale in (("H", r[0], g[0], nA), ("T", r[1], g[1], nB),
+                              ("Q", r[2], g[2], sq), ("Z", r[3], g[3], sq)):
+        d = a - b
+        out["max_" + name] = (float(np.abs(d).max()) if d.size else 0.0) / max(scale, 1e-300)
+        out["fro_" + name] = _fro(d) / max(scale, 1e-300)
+    return out
+
+
 def structure_violations(H, T):
     """Number of nonzero entries below H's subdiagonal and below T's diagonal
     (both must be exact zeros)."""

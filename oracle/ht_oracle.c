@@ -44,6 +44,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -635,11 +636,19 @@ int orc_fast_ht(int n, double *A, double *B, double *Q, double *Z, int ncols, ui
     orc_rot *rot = (orc_rot *)malloc(4 * N * sizeof(orc_rot));
 
     const double limit = timing && timing[0] > 0.0 ? timing[0] : 0.0;
+    /* optional progress lines on stderr (long runs): every 512 columns */
+    const int progress = getenv("HT_ORACLE_PROGRESS") != NULL;
     struct timespec ts0, ts1;
     clock_gettime(CLOCK_MONOTONIC, &ts0);
     int done = 0;
     for (int j = 0; j < ncols; j++) {
         const int o = j + 1, m = n - j - 1;
+        if (progress && j % 512 == 0 && j > 0) {
+            clock_gettime(CLOCK_MONOTONIC, &ts1);
+            fprintf(stderr, "O-fast n=%d: column %d of %d, %.1f s\n", n, j, ncols,
+                    (double)(ts1.tv_sec - ts0.tv_sec) + 1e-9 * (double)(ts1.tv_nsec - ts0.tv_nsec));
+            fflush(stderr);
+        }
         double *R = B + IDX(o, o, n);
         /* 1. left reflector F on A(j+1:n, j:n), accumulated in Q */
         double tau;

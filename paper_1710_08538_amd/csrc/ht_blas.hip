@@ -1,6 +1,8 @@
 // ht_blas.hip -- dense FP64 building blocks (GEMM, GEMV, TRMV, norms, copies)
 // used by the HouseHT driver.  All kernels are deterministic (fixed
 // reduction order, no floating-point atomics).
+#include <algorithm>
+
 #include "ht_device.h"
 #include "ht_internal.h"
 
@@ -9,95 +11,180 @@ namespace htk {
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
-// GEMM: C = alpha op(A) op(B) + beta C.  64x64 output tile per 256-thread
-// workgroup, each thread a 4x4 micro-tile, K staged through LDS in 16-wide
-// slices.
+// GEMM on the FP64 matrix cores: C = alpha op(A) op(B) + beta C.
+// A 256-thread workgroup computes a 64 x 64 tile of C; wavefront w owns the
+// 32 x 32 quarter (rows 32 (w & 1), columns 32 (w >> 1)) as 2 x 2 tiles of
+// v_mfma_f64_16x16x4f64.  The kernel forms the transposed tile
+// C^T = op(B)^T op(A)^T, whose accumulator layout (lane 16 g + c, register
+// i <-> row g + 4 i, column c of the 16 x 16 result) puts 16 consecutive
+// rows of one column of C in each lane group, so the stores are 128-byte
+// runs of the column-major C.  The contraction runs in chunks of 16: the
+// next chunk's op(A) (64 x 16) and op(B) (16 x 64) are loaded into
+// registers while the current chunk's MFMAs run from LDS, then stored to the
+// other LDS buffer (one barrier per chunk).  Out-of-range rows, columns and
+// contraction indices are staged as zeros.
+//
+// Split contraction: with gridDim.z = S > 1, slice z covers contraction
+// indices [z kc, min(k, (z + 1) kc)) and writes its raw sums to
+// part[z m n + j m + i]; k_gemm_reduce then adds the S slices in order and
+// applies alpha and beta, so results do not depend on timing.
 // ---------------------------------------------------------------------------
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(int m, int n, int k, double alpha,
-                                              const double* __restrict__ A, int lda,
-                                              const double* __restrict__ B, int ldb,
-                                              double beta, double* __restrict__ C, int ldc) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
-  const int tid = threadIdx.x;
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-  const int ti = tid & 15, tj = tid >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-  for (int k0 = 0; k0 < k; k0 += 16) {
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_mgemm(int m, int n, int k, int kc, double alpha,
+                                               const double* __restrict__ A, int lda,
+                                               const double* __restrict__ B, int ldb,
+                                               double beta, double* __restrict__ C, int ldc,
+                                               double* __restrict__ part) {
+  __shared__ double As[2][16][65];  // As[buf][kk][i] = op(A)(i0 + i, k0 + kk); padded rows
+  __shared__ double Bs[2][16][65];  // Bs[buf][kk][j] = op(B)(k0 + kk, j0 + j)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int kb = blockIdx.z * kc, ke = min(k, kb + kc);
+  const int wm = 32 * (wave & 1), wn = 32 * (wave >> 1);
+
+  // staging assignment: 1024 elements of each operand chunk, 4 per thread;
+  // the fast index follows the operand's contiguous dimension
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int rep = 0; rep < 4; ++rep) {
-      const int e = tid + rep * 256;
-      int kk, i;
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      int i, kk;
       if (!TA) { i = e & 63; kk = e >> 6; } else { kk = e & 15; i = e >> 4; }
+      const int gi = i0 + i, gk = k0 + kk;
       double v = 0.0;
-      if (i0 + i < m && k0 + kk < k)
-        v = TA ? A[(size_t)(k0 + kk) + (size_t)(i0 + i) * lda]
-               : A[(size_t)(i0 + i) + (size_t)(k0 + kk) * lda];
-      As[kk][i] = v;
-      int jj;
-      if (!TB) { kk = e & 15; jj = e >> 4; } else { jj = e & 63; kk = e >> 6; }
+      if (gi < m && gk < ke)
+        v = TA ? A[(size_t)gk + (size_t)gi * lda] : A[(size_t)gi + (size_t)gk * lda];
+      ra[r] = v;
+      int j;
+      if (!TB) { kk = e & 15; j = e >> 4; } else { j = e & 63; kk = e >> 6; }
+      const int gj = j0 + j, gk2 = k0 + kk;
       v = 0.0;
-      if (j0 + jj < n && k0 + kk < k)
-        v = TB ? B[(size_t)(j0 + jj) + (size_t)(k0 + kk) * ldb]
-               : B[(size_t)(k0 + kk) + (size_t)(j0 + jj) * ldb];
-      Bs[kk][jj] = v;
+      if (gj < n && gk2 < ke)
+        v = TB ? B[(size_t)gj + (size_t)gk2 * ldb] : B[(size_t)gk2 + (size_t)gj * ldb];
+      rb[r] = v;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[kk][ti + 16 * r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tj + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    for (int r = 0; r < 4; ++r) {
+      const int e = tid + 256 * r;
+      if (!TA) As[buf][e >> 6][e & 63] = ra[r];
+      else As[buf][e & 15][e >> 4] = ra[r];
+      if (!TB) Bs[buf][e & 15][e >> 4] = rb[r];
+      else Bs[buf][e >> 6][e & 63] = rb[r];
     }
+  };
+
+  v4d acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  if (kb < ke) {
+    load(kb);
+    store(0);
     __syncthreads();
+    int buf = 0;
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+      const bool more = k0 + 16 < ke;
+      if (more) load(k0 + 16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 4 * q + g;
+        // MFMA A operand: op(B)^T rows (columns of C), B operand: op(A)^T
+        const double b0 = Bs[buf][kk][wn + c], b1 = Bs[buf][kk][wn + 16 + c];
+        const double a0 = As[buf][kk][wm + c], a1 = As[buf][kk][wm + 16 + c];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc[1][1], 0, 0, 0);
+      }
+      if (more) store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
   }
+
+  // acc[y][x][r]: C(i0 + wm + 16 x + c, j0 + wn + 16 y + g + 4 r)
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + ti + 16 * r;
+  for (int x = 0; x < 2; ++x) {
+    const int i = i0 + wm + 16 * x + c;
     if (i >= m) continue;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = j0 + tj + 16 * c;
-      if (j >= n) continue;
-      double* p = C + (size_t)i + (size_t)j * ldc;
-      *p = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * *p);
-    }
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + wn + 16 * y + g + 4 * r;
+        if (j >= n) continue;
+        if (part) {
+          part[(size_t)blockIdx.z * m * n + (size_t)j * m + i] = acc[y][x][r];
+        } else {
+          double* p = C + (size_t)i + (size_t)j * ldc;
+          *p = (beta == 0.0) ? alpha * acc[y][x][r] : fma(alpha, acc[y][x][r], beta * *p);
+        }
+      }
   }
+}
+
+__global__ void k_gemm_reduce(int m, int n, int S, double alpha, const double* __restrict__ part,
+                              double beta, double* __restrict__ C, int ldc) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  double s = 0.0;
+  for (int z = 0; z < S; ++z) s += part[(size_t)z * m * n + e];
+  double* p = C + (size_t)i + (size_t)j * ldc;
+  *p = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * *p);
+}
+
+template <bool TA, bool TB>
+static void launch_mgemm(hipStream_t st, dim3 grid, int m, int n, int k, int kc, double alpha,
+                         const double* A, int lda, const double* B, int ldb, double beta,
+                         double* C, int ldc, double* part) {
+  hipLaunchKernelGGL((k_mgemm<TA, TB>), grid, dim3(256), 0, st, m, n, k, kc, alpha, A, lda, B,
+                     ldb, beta, C, ldc, part);
+}
+
+void gemm_ws(hipStream_t st, bool transA, bool transB, int m, int n, int k, double alpha,
+             const double* A, int lda, const double* B, int ldb, double beta, double* C,
+             int ldc, double* part, size_t part_doubles) {
+  if (m <= 0 || n <= 0) return;
+  if (k <= 0 && beta == 1.0) return;
+  const int kk = std::max(k, 0);
+  const int tiles = (int)(cdiv(m, 64) * cdiv(n, 64));
+  // split a long contraction over few output tiles (at least 512 indices
+  // per slice, at most what the partial-sum area holds)
+  int S = 1, kc = std::max(kk, 1);
+  if (part && tiles < 128 && kk >= 1024) {
+    const size_t cap = part_doubles / ((size_t)m * n);
+    S = (int)std::min<size_t>(cap, (size_t)std::min(256 / tiles, kk / 512));
+    if (S > 1) {
+      kc = (int)((cdiv(kk, S) + 15) / 16 * 16);
+      S = (int)cdiv(kk, kc);
+    }
+    if (S < 2) { S = 1; kc = std::max(kk, 1); }
+  }
+  dim3 grid(cdiv(m, 64), cdiv(n, 64), S);
+  double* pp = S > 1 ? part : nullptr;
+  if (!transA && !transB) launch_mgemm<false, false>(st, grid, m, n, kk, kc, alpha, A, lda, B, ldb, beta, C, ldc, pp);
+  else if (transA && !transB) launch_mgemm<true, false>(st, grid, m, n, kk, kc, alpha, A, lda, B, ldb, beta, C, ldc, pp);
+  else if (!transA && transB) launch_mgemm<false, true>(st, grid, m, n, kk, kc, alpha, A, lda, B, ldb, beta, C, ldc, pp);
+  else launch_mgemm<true, true>(st, grid, m, n, kk, kc, alpha, A, lda, B, ldb, beta, C, ldc, pp);
+  if (S > 1)
+    hipLaunchKernelGGL(k_gemm_reduce, dim3(cdiv((long)m * n, 256)), dim3(256), 0, st, m, n, S,
+                       alpha, part, beta, C, ldc);
 }
 
 void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k, double alpha,
           const double* A, int lda, const double* B, int ldb, double beta, double* C,
           int ldc) {
-  if (m <= 0 || n <= 0) return;
-  if (k <= 0) {
-    // C = beta C
-    if (beta == 1.0) return;
-    dim3 grid(cdiv(m, 64), cdiv(n, 64));
-    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, m, n, 0, 0.0, A,
-                       lda, B, ldb, beta, C, ldc);
-    return;
-  }
-  dim3 grid(cdiv(m, 64), cdiv(n, 64));
-  if (!transA && !transB)
-    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
-  else if (transA && !transB)
-    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
-  else if (!transA && transB)
-    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
-  else
-    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  gemm_ws(st, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "../../include/htred.h"
@@ -66,6 +67,7 @@ struct Work {
   double *acol_save, *ctil, *ysol, *dsol, *wv, *w2, *rv;
   double *tk, *tk2, *gk, *Ucat, *Kt, *Kt2, *P, *Wk;
   double* partials;
+  double* kpart;       // split-contraction sums of the WY products
   double* pool[4][2];  // chain transform pools: [chain][V or W]
   double* Gws;
   double* dscal;       // [0] tau_u, [1] beta_u, [2] normB, [3..4] IR norms, [5] tau_v, [6] beta_v
@@ -74,6 +76,9 @@ struct Work {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// slices of k x k partial sums for split-contraction WY products
+constexpr size_t kKpartSlices = 32;
 
 size_t layout(Work* w, int n, int nb, char* base) {
   size_t off = 0;
@@ -107,6 +112,7 @@ size_t layout(Work* w, int n, int nb, char* base) {
   w->P = take(N * 2 * K);
   w->Wk = take(N * K);
   w->partials = take(std::max<size_t>(((N + 511) / 512 + 1) * N, 64 * K));
+  w->kpart = take(kKpartSlices * K * K);
   const size_t poolsz = 2 * N * K + 4 * K * K;
   for (int c = 0; c < 4; ++c)
     for (int v = 0; v < 2; ++v) w->pool[c][v] = take(poolsz);
@@ -154,29 +160,61 @@ __global__ void k_check_finite(int m, int n, const double* X, int ld, int* bad) 
 
 inline double* at(double* X, int ld, int r, int c) { return X + (size_t)r + (size_t)c * ld; }
 
-// Per-kernel-class device timing with HIP events (HT_FLAG_PROFILE).  Events
-// come from a pool kept for the life of the process.
+// zero[j] = 1 when column j of the upper triangle of B is zero; *offdiag
+// becomes 1 when any strictly upper entry is nonzero (B not diagonal).
+__global__ void k_zero_columns(int n, const double* B, int ld, int* zero, int* offdiag) {
+  __shared__ int nz;
+  const int j = blockIdx.x;
+  if (threadIdx.x == 0) nz = 0;
+  __syncthreads();
+  int any = 0, off = 0;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    const bool z = B[(size_t)i + (size_t)j * ld] == 0.0;
+    any |= !z;
+    off |= (!z && i < j);
+  }
+  if (any) atomicOr(&nz, 1);
+  if (off) atomicOr(offdiag, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) zero[j] = nz ? 0 : 1;
+}
+
+// dst(i, j) = src(rp[i], cp[j]) (identity where rp / cp is NULL); with a
+// NULL src, src is the identity matrix.
+__global__ void k_gather(int n, const double* src, int lds, double* dst, int ldd, const int* rp,
+                         const int* cp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  const int si = rp ? rp[i] : i, sj = cp ? cp[j] : j;
+  dst[(size_t)i + (size_t)j * ldd] = src ? src[(size_t)si + (size_t)sj * lds] : (si == sj ? 1.0 : 0.0);
+}
+
+// Per-kernel-class device timing with HIP events (HT_FLAG_PROFILE).  The
+// events belong to the call: created on demand, destroyed by release() once
+// their times are read, so the library holds no HIP object between calls.
 struct Prof {
   bool on = false;
   struct Rec { int cls; hipEvent_t a, b; double work; };
   std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
   size_t used = 0;
-  static std::vector<hipEvent_t>& pool() {
-    static std::vector<hipEvent_t> p;
-    return p;
-  }
+  bool failed = false;
   hipEvent_t get() {
-    auto& p = pool();
-    if (used == p.size()) {
-      hipEvent_t e;
-      (void)hipEventCreate(&e);
-      p.push_back(e);
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) {
+        failed = true;
+        return nullptr;
+      }
+      pool.push_back(e);
     }
-    return p[used++];
+    return pool[used++];
   }
   int begin(hipStream_t st, int cls) {
-    if (!on) return -1;
+    if (!on || failed) return -1;
     Rec r{cls, get(), get(), 0.0};
+    if (!r.a || !r.b) return -1;
     (void)hipEventRecord(r.a, st);
     recs.push_back(r);
     return (int)recs.size() - 1;
@@ -193,6 +231,12 @@ struct Prof {
       s->prof_work[r.cls] += r.work;
       s->prof_launches[r.cls] += 1;
     }
+  }
+  void release() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    recs.clear();
+    used = 0;
   }
 };
 
@@ -217,7 +261,8 @@ struct Ctx {
 void wy(Ctx& c, bool ta, bool tb, int m, int n, int k, double alpha, const double* A, int lda,
         const double* B, int ldb, double beta, double* C, int ldc) {
   if (c.opt.prec == HT_PREC_FP64)
-    gemm(c.st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    gemm_ws(c.st, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, c.w->kpart,
+            kKpartSlices * (size_t)c.nb * c.nb);
   else
     split_gemm(c.st, c.opt.prec == HT_PREC_SPLIT_BF16 ? 0 : 1, c.opt.n_slices, ta, tb, m, n, k,
                alpha, A, lda, B, ldb, beta, C, ldc);
@@ -600,6 +645,51 @@ void absorb(Ctx& c, int s, int k) {
 }
 
 // ---------------------------------------------------------------------------
+// Householder QR of the columns [c0, c0 + ncols) of M, rows [r0, n), for the
+// steps before the reduction (the QR front end of the QZ algorithm, Sec. 1,
+// and the zero-column preprocessing of Sec. 3.5).  Panels of nb columns;
+// each panel is factored by a chain of window QRs from the bottom up, as U2
+// in Sec. 3.3.2 b (windows of 2 nb rows moving by nb, the R factor of one
+// window becoming the bottom of the next), so that its transformation is
+// the window sequence the absorption already applies: from the left to the
+// column ranges `lefts` (window rows only) and to the panel's own trailing
+// columns, and from the right to the columns r..n-1 of Q.
+// ---------------------------------------------------------------------------
+struct LRange { double* X; int ld; int cs; int ce; };  // columns [cs, ce) of X
+
+void qr_panels(Ctx& c, double* M, int ldm, int r0, int c0, int ncols,
+               const std::vector<LRange>& lefts) {
+  Work& w = *c.w;
+  const int n = c.n, nb = c.nb;
+  for (int p = 0; p < ncols; p += nb) {
+    const int r = r0 + p, col = c0 + p;
+    const int mp = n - r;
+    if (mp <= 1) break;
+    const int k = std::min(std::min(nb, ncols - p), mp);
+    const Blocks bl = make_blocks(mp, k, nb);
+    const int sb = bl.s, ldo = 2 * bl.s;
+    if (k < sb) {
+      const size_t slots = (size_t)(bl.T + 1) * 2 * sb * sb;
+      for (int v = 0; v < 2; ++v) zero_mat(c.st, w.pool[2][v], (int)slots, 1, (int)slots);
+    }
+    const std::vector<Win> wins = left_windows(bl, 2);
+    for (const Win& wn : wins)
+      chain(c, 0, false, wn.wdt, k, at(M, ldm, r + wn.a, col), ldm, tV(w, 2, wn, sb),
+            tW(w, 2, wn, sb), ldo);
+    std::vector<RJob> jobs;
+    if (col + k < c0 + ncols)
+      jobs.push_back(RJob{at(M, ldm, 0, col + k), ldm, c0 + ncols - col - k, false, col + k});
+    for (const LRange& lr : lefts)
+      if (lr.ce > lr.cs) jobs.push_back(RJob{at(lr.X, lr.ld, 0, lr.cs), lr.ld, lr.ce - lr.cs, false, lr.cs});
+    for (size_t i = 0; i < jobs.size(); i += 4) {
+      std::vector<RJob> part(jobs.begin() + i, jobs.begin() + std::min(jobs.size(), i + 4));
+      sweep_jobs(c, part, r - 1, bl, 2, wins, true);
+    }
+    if (c.wantQ) sweep_cols_right(c, c.Q, c.ldq, n, r - 1, bl, 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Algorithm 1.
 // ---------------------------------------------------------------------------
 int run(Ctx& c) {
@@ -611,7 +701,8 @@ int run(Ctx& c) {
   fro_norm(st, n, n, c.B, c.ldb, w.dscal + 2, w.partials);
   if (n <= 2) return 0;
 
-  int s = 0;
+  // columns before ilo are already in final form (ht_preprocess)
+  int s = c.opt.ilo;
   int64_t panel = 0;
   while (s <= n - 3) {
     const int L = n - s - 1;
@@ -735,6 +826,7 @@ static int resolve_opts(const ht_options* in, ht_options* out) {
   if (out->batch_wg_per_cu == 0) out->batch_wg_per_cu = 3;
   if (out->batch_block < 1 || out->batch_block > 64) return -10;
   if (out->batch_wg_per_cu < 1 || out->batch_wg_per_cu > 3) return -10;
+  if (out->ilo < 0) return -10;
   if (out->prec < HT_PREC_FP64 || out->prec > HT_PREC_SPLIT_FP8) return -10;
   if (out->prec != HT_PREC_FP64) {
     const int fmt = out->prec == HT_PREC_SPLIT_BF16 ? 0 : 1;
@@ -751,67 +843,99 @@ size_t ht_workspace_size(int64_t n, const ht_options* opt) {
   return layout(&w, (int)n, o.nb, nullptr) + 256;
 }
 
-int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda, int64_t ldb,
-              int64_t ldq, int64_t ldz, const ht_options* opt, ht_stats* stats, void* workspace,
-              size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Bytes of the device workspace for order n, panel width nb, including the
+// finite-scan flag at its end.
+size_t workspace_need(int n, int nb) {
+  Work w;
+  return layout(&w, n, nb, nullptr) + 256;
+}
+
+// The body of ht_reduce.  `ws` is the device workspace (the caller's, or
+// NULL: allocate).  With
+// `noalloc` nothing is allocated: the refinement verdict is read into
+// pageable host memory of this call, and profiling is refused.
+int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda, int64_t ldb,
+                int64_t ldq, int64_t ldz, const ht_options* opt, ht_stats* stats, char* ws,
+                size_t ws_bytes, hipStream_t st, bool noalloc) {
   const auto t0 = std::chrono::steady_clock::now();
   ht_options o;
   int rc = resolve_opts(opt, &o);
   if (rc) return rc;
   if (n < 0 || n > (int64_t)1 << 30) return -5;
   const int64_t ldmin = std::max<int64_t>(1, n);
-  if (lda < ldmin) return -6;
-  if (ldb < ldmin) return -7;
+  // leading dimensions are carried as 32-bit integers by the kernels
+  if (lda < ldmin || lda > INT32_MAX) return -6;
+  if (ldb < ldmin || ldb > INT32_MAX) return -7;
   const bool wantQ = o.qmode != HT_QZ_NONE, wantZ = o.zmode != HT_QZ_NONE;
-  if (wantQ && ldq < ldmin) return -8;
-  if (wantZ && ldz < ldmin) return -9;
+  if (wantQ && (ldq < ldmin || ldq > INT32_MAX)) return -8;
+  if (wantZ && (ldz < ldmin || ldz > INT32_MAX)) return -9;
   if (n > 0 && (!A || !B)) return !A ? -1 : -2;
   if (n > 0 && wantQ && !Q) return -3;
   if (n > 0 && wantZ && !Z) return -4;
-  if (o.qmode == HT_QZ_ACCUMULATE || o.zmode == HT_QZ_ACCUMULATE) return HT_ERR_UNSUPPORTED;
-  hipStream_t st = (hipStream_t)stream;
+  if (o.ilo > std::max<int64_t>(n, 0)) return -10;
+  if (noalloc && (o.flags & HT_FLAG_PROFILE)) return HT_ERR_UNSUPPORTED;
   if (stats) memset(stats, 0, sizeof(*stats));
   if (n == 0) return 0;
 
   const int ni = (int)n;
-  if (wantQ) set_identity(st, Q, ni, (int)ldq);
-  if (wantZ) set_identity(st, Z, ni, (int)ldz);
+  const size_t need = workspace_need(ni, o.nb);
+  char* base = ws;
+  bool owned = false;
+  if (base) {
+    if (ws_bytes < need || ((uintptr_t)base & 255)) return HT_ERR_WORKSPACE;
+  } else if (noalloc) {
+    return HT_ERR_WORKSPACE;
+  }
+
+  // Q and Z start as I unless the caller's Q_in, Z_in are to be
+  // accumulated: every update of Q and Z is a right multiplication over all
+  // n rows (Sec. 3.3.1 d, 3.3.2 d), so Q_in Q and Z_in Z come out directly.
+  if (wantQ && o.qmode == HT_QZ_IDENTITY) set_identity(st, Q, ni, (int)ldq);
+  if (wantZ && o.zmode == HT_QZ_IDENTITY) set_identity(st, Z, ni, (int)ldz);
+
+  // host memory for the refinement verdicts of this call: pinned (allocated
+  // and freed here), or in the no-allocation form a pageable array
+  int host_local[64] = {0};
+  int* pinned = nullptr;
+  if (!noalloc &&
+      hipHostMalloc((void**)&pinned, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return HT_ERR_HIP;
+  int* hints = pinned ? pinned : host_local;
+  auto finish = [&](int code) {
+    if (pinned) (void)hipHostFree(pinned);
+    return code;
+  };
 
   if (o.flags & HT_FLAG_CHECK_FINITE) {
     int* bad = nullptr;
-    if (hipMalloc(&bad, sizeof(int)) != hipSuccess) return HT_ERR_HIP;
+    if (base) {
+      bad = (int*)(base + need - 256);  // the flag word at the workspace's end
+    } else if (hipMalloc(&bad, sizeof(int)) != hipSuccess) {
+      return finish(HT_ERR_HIP);
+    }
     (void)hipMemsetAsync(bad, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_check_finite, dim3((ni + 255) / 256, ni), dim3(256), 0, st, ni, ni, A,
                        (int)lda, bad);
     hipLaunchKernelGGL(k_check_finite, dim3((ni + 255) / 256, ni), dim3(256), 0, st, ni, ni, B,
                        (int)ldb, bad);
-    int hbad = 0;
-    (void)hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(hints, bad, sizeof(int), hipMemcpyDeviceToHost, st);
     (void)hipStreamSynchronize(st);
-    (void)hipFree(bad);
-    if (hbad) return HT_ERR_NONFINITE;
+    if (!base) (void)hipFree(bad);
+    if (hints[0]) return finish(HT_ERR_NONFINITE);
   }
 
-  Work w;
-  const size_t need = layout(&w, ni, o.nb, nullptr) + 256;
-  char* base = (char*)workspace;
-  bool owned = false;
-  if (workspace) {
-    if (ws_bytes < need || ((uintptr_t)workspace & 255)) return HT_ERR_WORKSPACE;
-  } else {
-    if (hipMalloc((void**)&base, need) != hipSuccess) return HT_ERR_HIP;
+  if (!base) {
+    if (hipMalloc((void**)&base, need) != hipSuccess) return finish(HT_ERR_HIP);
     owned = true;
   }
+  Work w;
   layout(&w, ni, o.nb, base);
   (void)hipMemsetAsync(w.flags, 0, trsv_flag_bytes(ni), st);
 
-  static int* pinned = nullptr;
-  if (!pinned) {
-    if (hipHostMalloc((void**)&pinned, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
-      if (owned) (void)hipFree(base);
-      return HT_ERR_HIP;
-    }
-  }
   Ctx c;
   c.st = st;
   c.w = &w;
@@ -822,26 +946,219 @@ int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda
   c.wantQ = wantQ;
   c.wantZ = wantZ;
   c.opt = o;
-  c.host_ints = pinned;
+  c.host_ints = hints;
   c.prof.on = (o.flags & HT_FLAG_PROFILE) != 0 && stats != nullptr;
   rc = run(c);
   const hipError_t le = hipGetLastError();
   if (rc == 0 && le != hipSuccess) { g_last_hip = le; rc = HT_ERR_HIP; }
   if (stats || owned) (void)hipStreamSynchronize(st);
   if (stats) {
-    (void)hipMemcpy(pinned, w.ints, 8 * sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipMemcpyAsync(hints, w.ints, 8 * sizeof(int), hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
     stats->columns = c.columns;
     stats->cols_extra_ir = c.cols_extra_ir;
     stats->ir_steps = c.ir_steps;
     stats->ir_failures = c.ir_failures;
     stats->absorptions = c.absorptions;
-    stats->scaled_solves = pinned[5];
+    stats->scaled_solves = hints[5];
     stats->flops = c.flops;
     c.prof.collect(stats);
     stats->ms_total = std::chrono::duration<double, std::milli>(
         std::chrono::steady_clock::now() - t0).count();
   }
+  c.prof.release();
   if (owned) (void)hipFree(base);
+  return finish(rc);
+}
+
+// Workspace and context of the steps before the reduction (QR front end,
+// preprocessing): the same workspace as ht_reduce.  Returns HT_OK or an
+// error; on success the caller must call release().
+struct StepCall {
+  Work w;
+  Ctx c;
+  char* base = nullptr;
+  bool owned = false;
+  int host[64] = {0};
+  int release(int rc) {
+    if (owned) {
+      (void)hipStreamSynchronize(c.st);
+      (void)hipFree(base);
+    }
+    return rc;
+  }
+};
+
+int step_setup(StepCall& sc, double* A, double* B, double* Q, double* Z, int n, int lda, int ldb,
+               int ldq, int ldz, const ht_options& o, char* ws, size_t ws_bytes, hipStream_t st) {
+  const size_t need = workspace_need(n, o.nb);
+  sc.base = ws;
+  if (ws) {
+    if (ws_bytes < need || ((uintptr_t)ws & 255)) return HT_ERR_WORKSPACE;
+  } else {
+    if (hipMalloc((void**)&sc.base, need) != hipSuccess) return HT_ERR_HIP;
+    sc.owned = true;
+  }
+  layout(&sc.w, n, o.nb, sc.base);
+  Ctx& c = sc.c;
+  c.st = st;
+  c.w = &sc.w;
+  c.n = n;
+  c.nb = o.nb;
+  c.A = A; c.B = B; c.Q = Q; c.Z = Z;
+  c.lda = lda; c.ldb = ldb; c.ldq = ldq; c.ldz = ldz;
+  c.wantQ = o.qmode != HT_QZ_NONE;
+  c.wantZ = o.zmode != HT_QZ_NONE;
+  c.opt = o;
+  c.host_ints = sc.host;
+  return HT_OK;
+}
+
+// Common argument checks (argument positions as in ht_preprocess).
+int step_args(const ht_options* opt, ht_options* o, int64_t n, int64_t lda, int64_t ldb,
+              int64_t ldq, int64_t ldz, const double* A, const double* B, const double* Q,
+              const double* Z, bool useZ) {
+  const int rc = resolve_opts(opt, o);
+  if (rc) return rc;
+  if (o->prec != HT_PREC_FP64) return HT_ERR_UNSUPPORTED;
+  if (n < 0 || n > (int64_t)1 << 30) return -5;
+  const int64_t ldmin = std::max<int64_t>(1, n);
+  if (lda < ldmin || lda > INT32_MAX) return -6;
+  if (ldb < ldmin || ldb > INT32_MAX) return -7;
+  const bool wantQ = o->qmode != HT_QZ_NONE, wantZ = useZ && o->zmode != HT_QZ_NONE;
+  if (wantQ && (ldq < ldmin || ldq > INT32_MAX)) return -8;
+  if (wantZ && (ldz < ldmin || ldz > INT32_MAX)) return -9;
+  if (n > 0 && (!A || !B)) return !A ? -1 : -2;
+  if (n > 0 && wantQ && !Q) return -3;
+  if (n > 0 && wantZ && !Z) return -4;
+  return HT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda, int64_t ldb,
+              int64_t ldq, int64_t ldz, const ht_options* opt, ht_stats* stats, void* workspace,
+              size_t ws_bytes, void* stream) {
+  return reduce_impl(A, B, Q, Z, n, lda, ldb, ldq, ldz, opt, stats, (char*)workspace, ws_bytes,
+                     (hipStream_t)stream, false);
+}
+
+int ht_triangularize_b(double* A, double* B, double* Q, int64_t n, int64_t lda, int64_t ldb,
+                       int64_t ldq, const ht_options* opt, void* workspace, size_t ws_bytes,
+                       void* stream) {
+  ht_options o;
+  int rc = step_args(opt, &o, n, lda, ldb, ldq, 1, A, B, Q, nullptr, false);
+  if (rc) return rc;
+  if (n == 0) return HT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int ni = (int)n;
+  if (o.qmode == HT_QZ_IDENTITY) set_identity(st, Q, ni, (int)ldq);
+  StepCall sc;
+  o.zmode = HT_QZ_NONE;
+  rc = step_setup(sc, A, B, Q, nullptr, ni, (int)lda, (int)ldb, (int)ldq, 1, o, (char*)workspace,
+                  ws_bytes, st);
+  if (rc) return rc;
+  qr_panels(sc.c, B, (int)ldb, 0, 0, ni, {LRange{A, (int)lda, 0, ni}});
+  zero_lower(st, B, ni, (int)ldb, 0);
+  if (hipGetLastError() != hipSuccess) rc = HT_ERR_HIP;
+  return sc.release(rc);
+}
+
+int ht_preprocess(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda,
+                  int64_t ldb, int64_t ldq, int64_t ldz, const ht_options* opt, int32_t* ilo,
+                  void* workspace, size_t ws_bytes, void* stream) {
+  ht_options o;
+  int rc = step_args(opt, &o, n, lda, ldb, ldq, ldz, A, B, Q, Z, true);
+  if (rc) return rc;
+  if (!ilo) return -11;
+  *ilo = 0;
+  if (n == 0) return HT_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int ni = (int)n;
+  const bool wantQ = o.qmode != HT_QZ_NONE, wantZ = o.zmode != HT_QZ_NONE;
+
+  // which columns of B are zero, and is B diagonal (its strictly lower
+  // triangle is ignored, as by ht_reduce: cleared first)
+  zero_lower(st, B, ni, (int)ldb, 0);
+  int* dflags = nullptr;
+  if (hipMalloc((void**)&dflags, (size_t)(ni + 1) * sizeof(int)) != hipSuccess) return HT_ERR_HIP;
+  (void)hipMemsetAsync(dflags, 0, (size_t)(ni + 1) * sizeof(int), st);
+  hipLaunchKernelGGL(k_zero_columns, dim3(ni), dim3(256), 0, st, ni, B, (int)ldb, dflags,
+                     dflags + ni);
+  std::vector<int> zf((size_t)ni + 1);
+  if (hipMemcpyAsync(zf.data(), dflags, zf.size() * sizeof(int), hipMemcpyDeviceToHost, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipFree(dflags);
+    return HT_ERR_HIP;
+  }
+  std::vector<int> perm;
+  for (int j = 0; j < ni; ++j)
+    if (zf[j]) perm.push_back(j);
+  const int ell = (int)perm.size();
+  const bool diagonal = zf[ni] == 0;
+  if (ell <= 1) {  // the preprocessing needs more than one zero column
+    (void)hipFree(dflags);
+    if (wantQ && o.qmode == HT_QZ_IDENTITY) set_identity(st, Q, ni, (int)ldq);
+    if (wantZ && o.zmode == HT_QZ_IDENTITY) set_identity(st, Z, ni, (int)ldz);
+    return hipGetLastError() == hipSuccess ? HT_OK : HT_ERR_HIP;
+  }
+  for (int j = 0; j < ni; ++j)
+    if (!zf[j]) perm.push_back(j);
+
+  // Z0 moves the zero columns to the front; Q0 = Z0 when B is diagonal
+  int* dperm = dflags;  // reuse: n ints
+  double* tmp = nullptr;
+  rc = HT_OK;
+  if (hipMemcpyAsync(dperm, perm.data(), (size_t)ni * sizeof(int), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMalloc((void**)&tmp, (size_t)ni * ni * sizeof(double)) != hipSuccess)
+    rc = HT_ERR_HIP;
+  if (rc == HT_OK) {
+    const dim3 grid((ni + 255) / 256, ni);
+    const int* rp = diagonal ? dperm : nullptr;
+    double* M[2] = {A, B};
+    const int ldm[2] = {(int)lda, (int)ldb};
+    for (int t = 0; t < 2; ++t) {
+      copy_mat(st, ni, ni, M[t], ldm[t], tmp, ni);
+      hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, st, ni, tmp, ni, M[t], ldm[t], rp, dperm);
+    }
+    if (wantZ) {
+      const bool acc = o.zmode == HT_QZ_ACCUMULATE;
+      if (acc) copy_mat(st, ni, ni, Z, (int)ldz, tmp, ni);
+      hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, st, ni, acc ? tmp : nullptr, ni, Z,
+                         (int)ldz, nullptr, dperm);
+    }
+    if (wantQ) {
+      const bool acc = o.qmode == HT_QZ_ACCUMULATE;
+      if (diagonal) {
+        if (acc) copy_mat(st, ni, ni, Q, (int)ldq, tmp, ni);
+        hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, st, ni, acc ? tmp : nullptr, ni, Q,
+                           (int)ldq, nullptr, dperm);
+      } else if (!acc) {
+        set_identity(st, Q, ni, (int)ldq);
+      }
+    }
+    StepCall sc;
+    rc = step_setup(sc, A, B, Q, Z, ni, (int)lda, (int)ldb, (int)ldq, (int)ldz, o,
+                    (char*)workspace, ws_bytes, st);
+    if (rc == HT_OK) {
+      // QR of the first l columns of A0: A1 = [A11 A12; 0 A22], B1 = [0 B12; 0 B22]
+      qr_panels(sc.c, A, (int)lda, 0, 0, ell,
+                {LRange{A, (int)lda, ell, ni}, LRange{B, (int)ldb, ell, ni}});
+      // B22 made triangular again, its transformation applied to A22
+      qr_panels(sc.c, B, (int)ldb, ell, ell, ni - ell, {LRange{A, (int)lda, ell, ni}});
+      zero_lower(st, B, ni, (int)ldb, 0);
+      if (hipGetLastError() != hipSuccess) rc = HT_ERR_HIP;
+      rc = sc.release(rc);
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  if (tmp) (void)hipFree(tmp);
+  (void)hipFree(dflags);
+  if (rc == HT_OK) *ilo = ell;
   return rc;
 }
 

@@ -17,6 +17,13 @@ void gemm(hipStream_t st, bool transA, bool transB, int m, int n, int k,
           double alpha, const double* A, int lda, const double* B, int ldb,
           double beta, double* C, int ldc);
 
+// gemm with a partial-sum area of part_doubles doubles (may be NULL): a long
+// contraction over few output tiles is split into slices whose sums are
+// added in a fixed order by a second kernel.
+void gemm_ws(hipStream_t st, bool transA, bool transB, int m, int n, int k,
+             double alpha, const double* A, int lda, const double* B, int ldb,
+             double beta, double* C, int ldc, double* part, size_t part_doubles);
+
 // Emulated-FP64 product with the same contract as gemm, formed from ns
 // fixed-point digit slices per operand on the low-precision matrix cores:
 // fmt 0 = BF16 digits (7 bits, ns <= 8), fmt 1 = FP8 E4M3 digits (4 bits,

@@ -30,7 +30,8 @@ class Options(ctypes.Structure):
                 ("zmode", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("n_slices", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("ir_tol_factor", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("batch_block", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32)]
+                ("batch_block", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32),
+                ("ilo", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -72,6 +73,13 @@ def lib():
                                 ctypes.POINTER(Options), ctypes.POINTER(Stats), vp,
                                 ctypes.c_size_t, vp]
         L.ht_reduce.restype = ctypes.c_int
+        L.ht_triangularize_b.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.POINTER(Options),
+                                         vp, ctypes.c_size_t, vp]
+        L.ht_triangularize_b.restype = ctypes.c_int
+        L.ht_preprocess.argtypes = [vp, vp, vp, vp, i64, i64, i64, i64, i64,
+                                    ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_int32), vp,
+                                    ctypes.c_size_t, vp]
+        L.ht_preprocess.restype = ctypes.c_int
         L.ht_batched_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32,
                                                 ctypes.POINTER(Options)]
         L.ht_batched_workspace_size.restype = ctypes.c_size_t
@@ -135,44 +143,106 @@ def _check(rc):
         raise HTError("ht_reduce failed: %d (%s)" % (rc, msg))
 
 
-def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
-           prec=HT_PREC_FP64, n_slices=0, stats=False, workspace=None, stream=None,
-           check_finite=False, profile=False, solve_solo=False):
-    """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
+def _qz(X, mode, n, like, name):
+    """Output matrix for qmode/zmode: None (not computed) for HT_QZ_NONE,
+    else the caller's tensor (required for HT_QZ_ACCUMULATE) or a new one."""
+    if mode == HT_QZ_NONE:
+        return None, n if n > 0 else 1
+    if X is None:
+        if mode == HT_QZ_ACCUMULATE:
+            raise ValueError("%s_in is required with HT_QZ_ACCUMULATE" % name)
+        X = colmajor_empty(n, device=like.device)
+    return X, _ld(X, n, name)
 
-    A, B: n x n column-major float64 GPU tensors (B upper triangular).
-    Q, Z: optional preallocated outputs (allocated when None).
-    workspace: optional uint8 GPU tensor of >= workspace_size(n) bytes.
-    nb: panel width 1..128; 0 takes it from the autotuner's table
-        (``autotune.py``) for the nearest order, else the library default.
-    solve_solo: run every triangular solve on one workgroup (testing).
-    """
+
+def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, check_finite,
+                 profile, solve_solo, qmode, zmode, ilo=0):
     n = A.shape[0]
     lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
-    if Q is None:
-        Q = colmajor_empty(n, device=A.device)
-    if Z is None:
-        Z = colmajor_empty(n, device=A.device)
-    ldq, ldz = _ld(Q, n, "Q"), _ld(Z, n, "Z")
+    Q, ldq = _qz(Q, qmode, n, A, "Q")
+    Z, ldz = _qz(Z, zmode, n, A, "Z")
     if nb == 0:
         from paper_1710_08538_amd import autotune
         nb = autotune.pick_nb(n)
     o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
-                n_slices=n_slices, flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
+                n_slices=n_slices, qmode=qmode, zmode=zmode, ilo=ilo,
+                flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
                 | (HT_FLAG_PROFILE if profile else 0)
                 | (HT_FLAG_SOLVE_SOLO if solve_solo else 0))
+    ptrs = (A.data_ptr(), B.data_ptr(), Q.data_ptr() if Q is not None else None,
+            Z.data_ptr() if Z is not None else None, n, lda, ldb, ldq, ldz)
+    return Q, Z, o, ptrs
+
+
+def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
+           prec=HT_PREC_FP64, n_slices=0, stats=False, workspace=None, stream=None,
+           check_finite=False, profile=False, solve_solo=False, qmode=HT_QZ_IDENTITY,
+           zmode=HT_QZ_IDENTITY, ilo=0):
+    """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
+
+    A, B: n x n column-major float64 GPU tensors (B upper triangular).
+    Q, Z: optional preallocated outputs (allocated when None); with
+        qmode/zmode = HT_QZ_ACCUMULATE they hold Q_in, Z_in and receive
+        Q_in Q, Z_in Z; with HT_QZ_NONE they are not computed (None).
+    workspace: optional uint8 GPU tensor of >= workspace_size(n) bytes.
+    nb: panel width 1..128; 0 takes it from the autotuner's table
+        (``autotune.py``) for the nearest order, else the library default.
+    solve_solo: run every triangular solve on one workgroup (testing).
+    ilo: first column to reduce (columns before it already final, e.g. after
+        preprocess()).
+    """
+    Q, Z, o, ptrs = _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices,
+                                 check_finite, profile, solve_solo, qmode, zmode, ilo)
     st = Stats()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
-    rc = lib().ht_reduce(A.data_ptr(), B.data_ptr(), Q.data_ptr(), Z.data_ptr(), n, lda, ldb,
-                         ldq, ldz, ctypes.byref(o), ctypes.byref(st) if stats else None,
+    rc = lib().ht_reduce(*ptrs, ctypes.byref(o), ctypes.byref(st) if stats else None,
                          ws_ptr, ws_bytes, s.cuda_stream)
     _check(rc)
     if stats:
         return Q, Z, st.as_dict()
     return Q, Z
+
+
+def triangularize_b(A, B, Q=None, nb=64, qmode=HT_QZ_IDENTITY, workspace=None, stream=None):
+    """ht_triangularize_b: B <- R = Q0^T B (upper triangular), A <- Q0^T A;
+    returns Q (Q0, or Q_in Q0 with HT_QZ_ACCUMULATE; None with HT_QZ_NONE)."""
+    n = A.shape[0]
+    lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
+    Q, ldq = _qz(Q, qmode, n, A, "Q")
+    o = options(nb=nb, qmode=qmode)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    _check(lib().ht_triangularize_b(A.data_ptr(), B.data_ptr(),
+                                    Q.data_ptr() if Q is not None else None, n, lda, ldb, ldq,
+                                    ctypes.byref(o), ws_ptr, ws_bytes, s.cuda_stream))
+    return Q
+
+
+def preprocess(A, B, Q=None, Z=None, nb=64, qmode=HT_QZ_IDENTITY, zmode=HT_QZ_IDENTITY,
+               workspace=None, stream=None):
+    """ht_preprocess (zero columns of B moved to the front, Sec. 3.5); returns
+    (Q, Z, ilo).  Follow with reduce(A, B, Q, Z, ilo=ilo,
+    qmode=HT_QZ_ACCUMULATE, zmode=HT_QZ_ACCUMULATE)."""
+    n = A.shape[0]
+    lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
+    Q, ldq = _qz(Q, qmode, n, A, "Q")
+    Z, ldz = _qz(Z, zmode, n, A, "Z")
+    o = options(nb=nb, qmode=qmode, zmode=zmode)
+    ilo = ctypes.c_int32(0)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    _check(lib().ht_preprocess(A.data_ptr(), B.data_ptr(), Q.data_ptr() if Q is not None else None,
+                               Z.data_ptr() if Z is not None else None, n, lda, ldb, ldq, ldz,
+                               ctypes.byref(o), ctypes.byref(ilo), ws_ptr, ws_bytes,
+                               s.cuda_stream))
+    return Q, Z, ilo.value
 
 
 class BatchedPlan:

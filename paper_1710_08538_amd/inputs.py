@@ -18,6 +18,8 @@ always drawn before B's source):
 * ``batch_sizes`` / ``batch_pencil``: many independent small pencils with
   orders uniform in [32, 512] (HT reduction inside deflation windows, Sec. 1),
   pencil i seeded by ``SeedSequence(seed).spawn(count)[i]``.
+* ``zero_column_pencil``: random_pencil with some columns of B set to
+  zero (input of the zero-column preprocessing of Sec. 3.5).
 * ``saddle_pencil``: Test Suite 4 of Sec. 4 -- A = [X Y; Y^T 0],
   B = diag(I, 0) with X symmetric positive definite of order 3n/4.  Here X =
   G G^T / m + I with Gaussian G and Y Gaussian (the paper states only
@@ -73,6 +75,20 @@ def saddle_pencil(n, seed):
     A[m:, :m] = Y.T
     B = np.zeros((n, n))
     B[np.arange(m), np.arange(m)] = 1.0
+    return np.asfortranarray(A), np.asfortranarray(B)
+
+
+def zero_column_pencil(n, ell, seed):
+    """random_pencil(n, seed) with `ell` of B's columns (chosen uniformly,
+    drawn after A and B's source) set to zero: ell infinite eigenvalues and a
+    rank n - ell triangular B, the input of the zero-column preprocessing of
+    Sec. 3.5 with a nonsingular B22 afterwards."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    G = rng.standard_normal((n, n))
+    B = np.triu(np.linalg.qr(G, mode="r")) if n else G
+    cols = rng.choice(n, size=ell, replace=False) if ell else []
+    B[:, cols] = 0.0
     return np.asfortranarray(A), np.asfortranarray(B)
 
 

@@ -69,6 +69,47 @@ def test_argument_validation_without_device(L):
     assert L.ht_reduce(None, None, None, None, 10, 10, 10, 10, 10, ctypes.byref(o), None, None, 0, None) == -1
     # n == 0 is a valid no-op
     assert L.ht_reduce(None, None, None, None, 0, 1, 1, 1, 1, ctypes.byref(o), None, None, 0, None) == 0
+    # leading dimensions are 32-bit inside the kernels: larger ones are rejected
+    big = 1 << 31
+    for pos, lds in ((-6, (big, 10, 10, 10)), (-7, (10, big, 10, 10)), (-8, (10, 10, big, 10)),
+                     (-9, (10, 10, 10, big))):
+        assert L.ht_reduce(None, None, None, None, 10, *lds, ctypes.byref(o), None, None, 0,
+                           None) == pos, pos
+    # Q, Z not computed: their leading dimensions and pointers are ignored
+    none = htred.options(qmode=htred.HT_QZ_NONE, zmode=htred.HT_QZ_NONE)
+    assert L.ht_reduce(None, None, None, None, 10, 10, 10, 0, 0, ctypes.byref(none), None, None, 0,
+                       None) == -1
+    # accumulation needs Q_in / Z_in
+    acc = htred.options(qmode=htred.HT_QZ_ACCUMULATE)
+    p = ctypes.c_void_p(64)
+    assert L.ht_reduce(p, p, None, p, 10, 10, 10, 10, 10, ctypes.byref(acc), None, None, 0,
+                       None) == -3
+
+
+def test_front_end_argument_validation_without_device(L):
+    """ht_triangularize_b and ht_preprocess: argument checks before any
+    device work; n = 0 is a no-op; split precisions are refused."""
+    from paper_1710_08538_amd import htred
+    o = htred.options()
+    ilo = ctypes.c_int32(7)
+    T, P = L.ht_triangularize_b, L.ht_preprocess
+    assert T(None, None, None, -1, 1, 1, 1, ctypes.byref(o), None, 0, None) == -5
+    assert T(None, None, None, 10, 9, 10, 10, ctypes.byref(o), None, 0, None) == -6
+    assert T(None, None, None, 10, 10, 9, 10, ctypes.byref(o), None, 0, None) == -7
+    assert T(None, None, None, 10, 10, 10, 9, ctypes.byref(o), None, 0, None) == -8
+    assert T(None, None, None, 10, 10, 10, 10, ctypes.byref(o), None, 0, None) == -1
+    assert T(None, None, None, 0, 1, 1, 1, ctypes.byref(o), None, 0, None) == 0
+    split = htred.options(prec=htred.HT_PREC_SPLIT_BF16)
+    assert T(None, None, None, 10, 10, 10, 10, ctypes.byref(split), None, 0, None) == \
+        htred.HT_ERR_UNSUPPORTED
+    assert P(None, None, None, None, 10, 10, 10, 10, 9, ctypes.byref(o), ctypes.byref(ilo), None,
+             0, None) == -9
+    p = ctypes.c_void_p(64)
+    assert P(p, p, p, None, 10, 10, 10, 10, 10, ctypes.byref(o), ctypes.byref(ilo), None, 0,
+             None) == -4
+    assert P(p, p, p, p, 10, 10, 10, 10, 10, ctypes.byref(o), None, None, 0, None) == -11
+    assert P(None, None, None, None, 0, 1, 1, 1, 1, ctypes.byref(o), ctypes.byref(ilo), None, 0,
+             None) == 0 and ilo.value == 0
 
 
 def test_strerror(L):
@@ -191,14 +232,14 @@ def test_compute_calls_fail_without_a_gpu():
                        timeout=120)
     assert r.returncode == 0, r.stderr
     from paper_1710_08538_amd import htred
-    assert [int(x) for x in r.stdout.split()] == [htred.HT_ERR_HIP, htred.HT_ERR_HIP]
+    assert [int(x) for x in r.stdout.split()] == [htred.HT_ERR_HIP] * 2
 
 
 def test_return_codes_match_the_header():
     from paper_1710_08538_amd import htred
     hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                             "include", "htred.h")).read()
-    codes = dict(re.findall(r"#define (HT_(?:OK|ERR_[A-Z]+))\s+(\d+)", hdr))
+    codes = dict(re.findall(r"#define (HT_(?:OK|ERR_[A-Z_]+))\s+(\d+)", hdr))
     assert len(codes) == 6
     for name, val in codes.items():
         assert getattr(htred, name) == int(val), name
@@ -223,4 +264,4 @@ def test_every_declaration_is_documented_and_cited():
             assert "no passage of the paper" in block, name
         else:
             assert cite.search(block), name
-    assert len(names) == 10
+    assert len(names) == 12

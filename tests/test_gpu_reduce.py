@@ -203,25 +203,6 @@ def test_solo_solves_illconditioned():
     assert_invariants(A0, B0, got)
 
 
-@pytest.mark.parametrize("nb", [32, 64, 128])
-def test_config_n4096(nb):
-    """Full-size n = 4096 pencil: invariants on the whole output (device
-    products), parity of the first 12 columns with a 12-step oracle run."""
-    A0, B0 = inputs.workload("n4096")
-    n = A0.shape[0]
-    A = htred.to_device_colmajor(A0)
-    B = htred.to_device_colmajor(B0)
-    print("ht_reduce n=4096 nb=%d" % nb, flush=True)
-    Q, Z = htred.reduce(A, B, nb=nb)
-    Ad, Bd = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
-    inv = checks.invariants(Ad, Bd, A, B, Q, Z)
-    assert checks.invariants_ok(inv, n), inv
-    c = 12
-    ref = oracle.ms_ht(A0, B0, ncols=c)
-    got = tuple(x.cpu().numpy() for x in (A, B, Q, Z))
-    assert_parity(ref, got, A0, B0, upto=c)
-
-
 def test_config_n16384_illcond_full_size():
     """The headline pencil at its full size in the configuration bench.py
     times (n = 16384, ill-conditioned B, nb = 128): the invariants on the
@@ -316,3 +297,94 @@ def test_saddle_point_pencils(n, nb):
     got = (A.cpu().numpy(), B.cpu().numpy(), Qs[0].cpu().numpy(), Zs[0].cpu().numpy())
     inv = checks.invariants(A0, B0, *got)
     assert checks.invariants_ok(inv, n), inv
+
+
+def _orthogonal(n, seed):
+    G = np.random.default_rng(seed).standard_normal((n, n))
+    return np.asfortranarray(np.linalg.qr(G)[0])
+
+
+def test_qz_modes_and_padded_leading_dimensions():
+    """HT_QZ_NONE leaves Q and Z alone and gives bitwise the same H and T
+    (A and B never read Q or Z); Q and Z with a padded leading dimension
+    (ld = n + 7) give bitwise the same Q, Z and leave the padding untouched;
+    HT_QZ_ACCUMULATE with orthogonal Q_in, Z_in gives Q_in Q and Z_in Z up
+    to rounding, and again the same H and T."""
+    n, nb = 190, 32
+    A0, B0 = inputs.random_pencil(n, seed=31)
+    ref, _ = run_gpu(A0, B0, nb=nb)
+
+    print("ht_reduce qmode=zmode=NONE n=%d" % n, flush=True)
+    A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    Q, Z = htred.reduce(A, B, nb=nb, qmode=htred.HT_QZ_NONE, zmode=htred.HT_QZ_NONE)
+    torch.cuda.synchronize()
+    assert Q is None and Z is None
+    assert np.array_equal(A.cpu().numpy(), ref[0]) and np.array_equal(B.cpu().numpy(), ref[1])
+
+    print("ht_reduce padded Q/Z n=%d" % n, flush=True)
+    ld = n + 7
+    Qd = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda").t()
+    Zd = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda").t()
+    A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    htred.reduce(A, B, Qd[:n], Zd[:n], nb=nb)
+    torch.cuda.synchronize()
+    assert np.array_equal(Qd[:n].cpu().numpy(), ref[2]) and np.array_equal(Zd[:n].cpu().numpy(), ref[3])
+    assert bool((Qd[n:] == 7.0).all()) and bool((Zd[n:] == 7.0).all())
+
+    print("ht_reduce qmode=zmode=ACCUMULATE n=%d" % n, flush=True)
+    Qi, Zi = _orthogonal(n, 32), _orthogonal(n, 33)
+    A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    Q, Z = htred.to_device_colmajor(Qi), htred.to_device_colmajor(Zi)
+    htred.reduce(A, B, Q, Z, nb=nb, qmode=htred.HT_QZ_ACCUMULATE, zmode=htred.HT_QZ_ACCUMULATE)
+    torch.cuda.synchronize()
+    assert np.array_equal(A.cpu().numpy(), ref[0]) and np.array_equal(B.cpu().numpy(), ref[1])
+    assert np.abs(Q.cpu().numpy() - Qi @ ref[2]).max() <= 1e-13 * n
+    assert np.abs(Z.cpu().numpy() - Zi @ ref[3]).max() <= 1e-13 * n
+    # the accumulated pencil: (Q_in H Z_in^T... ) reproduces Q_in A Z_in^T's reduction
+    got = (A.cpu().numpy(), B.cpu().numpy(), Q.cpu().numpy(), Z.cpu().numpy())
+    inv = checks.invariants(Qi @ A0 @ Zi.T, Qi @ B0 @ Zi.T, *got)
+    assert inv["bwd_A"] <= 1e-14 * n and inv["bwd_B"] <= 1e-14 * n, inv
+    assert inv["orth_Q"] <= 1e-13 * n and inv["orth_Z"] <= 1e-13 * n, inv
+
+
+def test_concurrent_calls_on_two_streams():
+    """Two host threads reduce two pencils at once, each on its own stream
+    and workspace: every call keeps its own refinement verdicts, so both
+    results are bitwise those of the same calls made one after the other.
+    The pencils are ill-conditioned, so both calls refine and cut panels."""
+    import threading
+    n, nb = 400, 32
+    pens = [inputs.illcond_pencil(n, seed=s) for s in (41, 42)]
+    seq = [run_gpu(A0, B0, nb=nb)[0] for A0, B0 in pens]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    bufs = []
+    for A0, B0 in pens:
+        A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+        Q, Z = htred.colmajor_empty(n), htred.colmajor_empty(n)
+        ws = torch.empty(htred.workspace_size(n, nb=nb), dtype=torch.uint8, device="cuda")
+        bufs.append((A, B, Q, Z, ws))
+    torch.cuda.synchronize()
+    stats = [None, None]
+    errs = []
+
+    def work(i):
+        try:
+            A, B, Q, Z, ws = bufs[i]
+            stats[i] = htred.reduce(A, B, Q, Z, nb=nb, workspace=ws, stream=streams[i],
+                                    stats=True)[2]
+        except Exception as e:  # noqa: BLE001
+            errs.append(e)
+
+    print("ht_reduce two threads n=%d" % n, flush=True)
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errs, errs
+    assert all(s["cols_extra_ir"] > 0 for s in stats), stats
+    for i in range(2):
+        got = tuple(M.cpu().numpy() for M in bufs[i][:4])
+        for x, y in zip(got, seq[i]):
+            assert np.array_equal(x, y), i

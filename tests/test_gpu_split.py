@@ -119,6 +119,25 @@ def test_fp64_path_of_wy_gemm():
     np.testing.assert_allclose(got, A @ B, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("m,k,n", [(1, 1, 1), (64, 16, 64), (130, 77, 45), (200, 300, 129),
+                                   (17, 1000, 33), (300, 5, 260), (65, 0, 63)])
+def test_fp64_wy_gemm_exact(ta, tb, m, k, n):
+    """The FP64 matrix-core product on operands whose products and sums are
+    exact in FP64 (small integers times powers of two): every entry equals
+    the exact result, for the four transposition variants, ragged tiles and
+    chunks, and an empty contraction (C = beta C)."""
+    rng = np.random.default_rng(m * 7 + k * 3 + n)
+    A = rng.integers(-7, 8, size=(m, k)).astype(np.float64) * np.exp2(rng.integers(-20, 20, (m, 1)))
+    B = rng.integers(-2 ** 20, 2 ** 20, size=(k, n)).astype(np.float64) * \
+        np.exp2(rng.integers(-20, 20, (1, n)))
+    C0 = rng.integers(-2 ** 20, 2 ** 20, size=(m, n)).astype(np.float64)
+    got = run_gemm(A, B, ta, tb, htred.HT_PREC_FP64, 0)
+    assert np.array_equal(got, A @ B)
+    got = run_gemm(A, B, ta, tb, htred.HT_PREC_FP64, 0, C0=C0, alpha=-2.0, beta=0.5)
+    assert np.array_equal(got, -2.0 * (A @ B) + 0.5 * C0)
+
+
 def run_reduce(A0, B0, **kw):
     print("ht_reduce n=%d %s" % (A0.shape[0], kw), flush=True)
     A, B = dev(A0), dev(B0)
