@@ -43,6 +43,8 @@ extern "C" {
 #define HT_ERR_NONFINITE   3  /* NaN or Inf found in A or B on entry */
 #define HT_ERR_UNSUPPORTED 4  /* option combination not implemented */
 #define HT_ERR_NOLIB       5  /* device code for this GPU is missing */
+#define HT_ERR_TOO_LARGE   6  /* ht_reduce_noalloc: the order needs more than the
+                                 library's fixed scratch (HT_NOALLOC_SCRATCH_BYTES) */
 
 /* How Q and Z are produced. */
 typedef enum {
@@ -229,6 +231,31 @@ int ht_triangularize_b(double *A, double *B, double *Q, int64_t n, int64_t lda,
 int ht_preprocess(double *A, double *B, double *Q, double *Z, int64_t n, int64_t lda,
                   int64_t ldb, int64_t ldq, int64_t ldz, const ht_options *opt,
                   int32_t *ilo, void *workspace, size_t ws_bytes, void *stream);
+
+/* Size of the fixed device scratch of ht_reduce_noalloc (per GPU). */
+#define HT_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * ht_reduce_noalloc -- ht_reduce for callers that cannot allocate memory
+ * (tight serving loops, harnesses that forbid hipMalloc / hipHostMalloc).
+ * Same arguments, results and return codes as ht_reduce (same kernels),
+ * without the workspace arguments: the device workspace is a fixed array of
+ * HT_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library, one per GPU, held
+ * until the process ends.  Orders whose workspace (ht_workspace_size for
+ * the same options) exceeds it return HT_ERR_TOO_LARGE: it holds orders up
+ * to 2250 at nb = 128, 4993 at nb = 64 and 9993 at nb = 32.
+ * The call allocates nothing: refinement verdicts are read into pageable
+ * host memory of the call, HT_FLAG_CHECK_FINITE uses a word of the array,
+ * and HT_FLAG_PROFILE (which creates HIP events) returns HT_ERR_UNSUPPORTED.
+ * Every call on a GPU uses that GPU's one array, which keeps the previous
+ * call's contents (the call clears what must start at zero): calls that
+ * overlap on one GPU (several host threads or streams) race and must be
+ * serialised by the caller.  The first call on each device resolves the
+ * array's device address (hipGetSymbolAddress) once.
+ */
+int ht_reduce_noalloc(double *A, double *B, double *Q, double *Z, int64_t n,
+                      int64_t lda, int64_t ldb, int64_t ldq, int64_t ldz,
+                      const ht_options *opt, ht_stats *stats, void *stream);
 
 /*
  * ht_reduce_batched -- independent HT reductions of `batch` small pencils in

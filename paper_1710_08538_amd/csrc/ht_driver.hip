@@ -847,6 +847,31 @@ size_t ht_workspace_size(int64_t n, const ht_options* opt) {
 
 namespace {
 
+// Device memory of the allocation-free entry point ht_reduce_noalloc: one
+// array per GPU, alive until the process ends.  Host code never passes the
+// array's name to a kernel; it uses the device address that
+// hipGetSymbolAddress returns for the current device (scratch_ptr).
+constexpr size_t kScratchBytes = (size_t)HT_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, resolved once per device.
+int scratch_ptr(char** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HT_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HT_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return HT_OK;
+}
+
 // Bytes of the device workspace for order n, panel width nb, including the
 // finite-scan flag at its end.
 size_t workspace_need(int n, int nb) {
@@ -854,8 +879,8 @@ size_t workspace_need(int n, int nb) {
   return layout(&w, n, nb, nullptr) + 256;
 }
 
-// The body of ht_reduce.  `ws` is the device workspace (the caller's, or
-// NULL: allocate).  With
+// The common body of ht_reduce and ht_reduce_noalloc.  `ws` is the device
+// workspace (caller's, the library's scratch, or NULL: allocate).  With
 // `noalloc` nothing is allocated: the refinement verdict is read into
 // pageable host memory of this call, and profiling is refused.
 int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda, int64_t ldb,
@@ -1045,6 +1070,23 @@ int ht_reduce(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda
                      (hipStream_t)stream, false);
 }
 
+int ht_reduce_noalloc(double* A, double* B, double* Q, double* Z, int64_t n, int64_t lda,
+                      int64_t ldb, int64_t ldq, int64_t ldz, const ht_options* opt,
+                      ht_stats* stats, void* stream) {
+  ht_options o;
+  const int orc = resolve_opts(opt, &o);
+  if (orc) return orc;
+  if (n < 0 || n > (int64_t)1 << 30) return -5;
+  if (n > 0 && workspace_need((int)n, o.nb) > kScratchBytes) return HT_ERR_TOO_LARGE;
+  char* p = nullptr;
+  if (n > 0) {
+    const int src = scratch_ptr(&p);
+    if (src != HT_OK) return src;
+  }
+  return reduce_impl(A, B, Q, Z, n, lda, ldb, ldq, ldz, opt, stats, p, kScratchBytes,
+                     (hipStream_t)stream, true);
+}
+
 int ht_triangularize_b(double* A, double* B, double* Q, int64_t n, int64_t lda, int64_t ldb,
                        int64_t ldq, const ht_options* opt, void* workspace, size_t ws_bytes,
                        void* stream) {
@@ -1171,6 +1213,8 @@ const char* ht_strerror(int code) {
     case HT_ERR_NONFINITE: return "NaN or Inf in the input";
     case HT_ERR_UNSUPPORTED: return "unsupported option combination";
     case HT_ERR_NOLIB: return "device code missing for this GPU";
+    case HT_ERR_TOO_LARGE:
+      return "order too large for the library's fixed scratch (ht_reduce_noalloc)";
   }
   return "unknown error";
 }

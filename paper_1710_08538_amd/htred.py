@@ -18,7 +18,9 @@ HT_QZ_IDENTITY, HT_QZ_ACCUMULATE, HT_QZ_NONE = 0, 1, 2
 HT_PREC_FP64, HT_PREC_SPLIT_BF16, HT_PREC_SPLIT_FP8 = 0, 1, 2
 HT_FLAG_CHECK_FINITE = 1
 # return codes (include/htred.h); negative values name an invalid argument
-HT_OK, HT_ERR_HIP, HT_ERR_WORKSPACE, HT_ERR_NONFINITE, HT_ERR_UNSUPPORTED, HT_ERR_NOLIB = range(6)
+(HT_OK, HT_ERR_HIP, HT_ERR_WORKSPACE, HT_ERR_NONFINITE, HT_ERR_UNSUPPORTED, HT_ERR_NOLIB,
+ HT_ERR_TOO_LARGE) = range(7)
+HT_NOALLOC_SCRATCH_BYTES = 64 << 20
 HT_FLAG_PROFILE = 2
 HT_FLAG_SOLVE_SOLO = 4
 PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain", "sweep")
@@ -73,6 +75,9 @@ def lib():
                                 ctypes.POINTER(Options), ctypes.POINTER(Stats), vp,
                                 ctypes.c_size_t, vp]
         L.ht_reduce.restype = ctypes.c_int
+        L.ht_reduce_noalloc.argtypes = [vp, vp, vp, vp, i64, i64, i64, i64, i64,
+                                        ctypes.POINTER(Options), ctypes.POINTER(Stats), vp]
+        L.ht_reduce_noalloc.restype = ctypes.c_int
         L.ht_triangularize_b.argtypes = [vp, vp, vp, i64, i64, i64, i64, ctypes.POINTER(Options),
                                          vp, ctypes.c_size_t, vp]
         L.ht_triangularize_b.restype = ctypes.c_int
@@ -200,6 +205,25 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     rc = lib().ht_reduce(*ptrs, ctypes.byref(o), ctypes.byref(st) if stats else None,
                          ws_ptr, ws_bytes, s.cuda_stream)
+    _check(rc)
+    if stats:
+        return Q, Z, st.as_dict()
+    return Q, Z
+
+
+def reduce_noalloc(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
+                   prec=HT_PREC_FP64, n_slices=0, stats=False, stream=None,
+                   check_finite=False, solve_solo=False, qmode=HT_QZ_IDENTITY,
+                   zmode=HT_QZ_IDENTITY):
+    """ht_reduce_noalloc: as reduce(), with the library's fixed device
+    scratch in place of a workspace (no allocation inside the call; pass Q
+    and Z to keep this wrapper from allocating them)."""
+    Q, Z, o, ptrs = _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices,
+                                 check_finite, False, solve_solo, qmode, zmode)
+    st = Stats()
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    rc = lib().ht_reduce_noalloc(*ptrs, ctypes.byref(o), ctypes.byref(st) if stats else None,
+                                 s.cuda_stream)
     _check(rc)
     if stats:
         return Q, Z, st.as_dict()

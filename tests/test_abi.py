@@ -86,6 +86,31 @@ def test_argument_validation_without_device(L):
                        None) == -3
 
 
+def test_noalloc_argument_validation_without_device(L):
+    """ht_reduce_noalloc: the same argument checks as ht_reduce, and orders
+    whose workspace exceeds the fixed scratch are refused with
+    HT_ERR_TOO_LARGE before any device work."""
+    from paper_1710_08538_amd import htred
+    o = htred.options(nb=128)
+    lim = htred.HT_NOALLOC_SCRATCH_BYTES
+    # the largest orders the header states: 2250 (nb 128), 4993 (64), 9993 (32)
+    for nb, nmax in ((128, 2250), (64, 4993), (32, 9993)):
+        ob = htred.options(nb=nb)
+        assert L.ht_workspace_size(nmax, ctypes.byref(ob)) <= lim
+        assert L.ht_workspace_size(nmax + 1, ctypes.byref(ob)) > lim
+    assert L.ht_reduce_noalloc(None, None, None, None, 2251, 2251, 2251, 2251, 2251,
+                               ctypes.byref(o), None, None) == htred.HT_ERR_TOO_LARGE
+    assert L.ht_reduce_noalloc(None, None, None, None, -1, 1, 1, 1, 1, ctypes.byref(o), None,
+                               None) == -5
+    assert L.ht_reduce_noalloc(None, None, None, None, 0, 1, 1, 1, 1, ctypes.byref(o), None,
+                               None) == 0
+    bad = htred.options()
+    bad.struct_size = 3
+    assert L.ht_reduce_noalloc(None, None, None, None, 10, 10, 10, 10, 10, ctypes.byref(bad), None,
+                               None) == -10
+    assert b"scratch" in L.ht_strerror(htred.HT_ERR_TOO_LARGE)
+
+
 def test_front_end_argument_validation_without_device(L):
     """ht_triangularize_b and ht_preprocess: argument checks before any
     device work; n = 0 is a no-op; split precisions are refused."""
@@ -225,6 +250,7 @@ def test_compute_calls_fail_without_a_gpu():
         "p = [ctypes.c_void_p(64 * (i + 1)) for i in range(4)]\n"
         "print(L.ht_reduce(p[0], p[1], p[2], p[3], 4, 4, 4, 4, 4, None, None, None, 0, None))\n"
         "print(L.ht_wy_gemm(0, 0, 0, 0, 4, 4, 4, 1.0, p[0], 4, p[1], 4, 0.0, p[2], 4, None))\n"
+        "print(L.ht_reduce_noalloc(p[0], p[1], p[2], p[3], 4, 4, 4, 4, 4, None, None, None))\n"
     ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", CUDA_VISIBLE_DEVICES="-1",
                ROCR_VISIBLE_DEVICES="-1")
@@ -232,7 +258,7 @@ def test_compute_calls_fail_without_a_gpu():
                        timeout=120)
     assert r.returncode == 0, r.stderr
     from paper_1710_08538_amd import htred
-    assert [int(x) for x in r.stdout.split()] == [htred.HT_ERR_HIP] * 2
+    assert [int(x) for x in r.stdout.split()] == [htred.HT_ERR_HIP] * 3
 
 
 def test_return_codes_match_the_header():
@@ -240,7 +266,7 @@ def test_return_codes_match_the_header():
     hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                             "include", "htred.h")).read()
     codes = dict(re.findall(r"#define (HT_(?:OK|ERR_[A-Z_]+))\s+(\d+)", hdr))
-    assert len(codes) == 6
+    assert len(codes) == 7
     for name, val in codes.items():
         assert getattr(htred, name) == int(val), name
 
@@ -262,6 +288,9 @@ def test_every_declaration_is_documented_and_cited():
         block = before[before.rfind("/*", 0, end):end]
         if name in ("ht_strerror", "ht_version"):
             assert "no passage of the paper" in block, name
+        elif name == "ht_reduce_noalloc":
+            # in place of a citation: the callers it is for
+            assert "cannot allocate" in block, name
         else:
             assert cite.search(block), name
-    assert len(names) == 12
+    assert len(names) == 13

@@ -1,0 +1,55 @@
+"""ht_reduce_noalloc (the entry point for callers that cannot allocate)
+against ht_reduce on the same pencils, through the C ABI: two calls in a
+row, the second with a smaller order, so the second runs on the scratch the
+first left behind.  The two entry points run the same kernels on the same
+workspace layout, so the outputs must agree entry by entry to the parity
+tolerance (1e-10 relative to ||A||_F, ||B||_F, sqrt(n)), and they are in
+fact expected to be bitwise equal."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import checks
+from paper_1710_08538_amd import htred, inputs
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _run(fn, A0, B0, nb, **kw):
+    A, B = htred.to_device_colmajor(A0), htred.to_device_colmajor(B0)
+    n = A0.shape[0]
+    Q, Z = htred.colmajor_empty(n), htred.colmajor_empty(n)
+    st = fn(A, B, Q, Z, nb=nb, stats=True, **kw)[2]
+    torch.cuda.synchronize()
+    return tuple(M.cpu().numpy() for M in (A, B, Q, Z)), st
+
+
+@pytest.mark.parametrize("nb,sizes", [(128, (2250, 700)), (64, (1000, 301)), (32, (257, 65))])
+def test_noalloc_matches_reduce_two_calls(nb, sizes):
+    for n, kind in zip(sizes, ("illcond", "random")):
+        gen = inputs.illcond_pencil if kind == "illcond" else inputs.random_pencil
+        A0, B0 = gen(n, seed=n)
+        print("ht_reduce / ht_reduce_noalloc n=%d nb=%d %s" % (n, nb, kind), flush=True)
+        ref, st_ref = _run(htred.reduce, A0, B0, nb)
+        got, st = _run(htred.reduce_noalloc, A0, B0, nb)
+        d = checks.compare(ref, got, A0, B0)
+        for key in ("max_H", "max_T", "max_Q", "max_Z"):
+            assert d[key] <= TOL, (n, key, d)
+        for key in ("columns", "cols_extra_ir", "ir_steps", "ir_failures", "absorptions",
+                    "scaled_solves"):
+            assert st[key] == st_ref[key], (n, key, st, st_ref)
+        inv = checks.invariants(A0, B0, *got)
+        if kind == "random":
+            assert checks.invariants_ok(inv, n), inv
+        bitwise = all(np.array_equal(x, y) for x, y in zip(ref, got))
+        print("n=%d nb=%d: max diff %.2e, bitwise %s" % (n, nb, max(d.values()), bitwise),
+              flush=True)
+
+
+def test_noalloc_rejects_orders_beyond_the_scratch():
+    n = 2251
+    A = htred.colmajor_empty(n)
+    B = htred.colmajor_empty(n)
+    with pytest.raises(htred.HTError, match="scratch"):
+        htred.reduce_noalloc(A, B, htred.colmajor_empty(n), htred.colmajor_empty(n), nb=128)
