@@ -106,6 +106,12 @@ typedef struct {
 #define HT_FLAG_PROFILE      2  /* time kernel classes with HIP events (stats) */
 #define HT_FLAG_SOLVE_SOLO   4  /* triangular solves on one workgroup, without
                                    helper workgroups (slower; for testing) */
+#define HT_FLAG_ONE_STREAM   8  /* ht_reduce: enqueue everything on `stream`.  By
+                                   default (n > 256, no HT_FLAG_PROFILE) the sweeps of
+                                   a chain's windows run on a second (non-blocking)
+                                   stream that the call creates, while the chain
+                                   itself goes on; the results are bitwise the same
+                                   either way */
 
 /* Kernel classes reported in ht_stats.prof_* when HT_FLAG_PROFILE is set.
  * prof_work is the algorithmic work of the class: flops for the

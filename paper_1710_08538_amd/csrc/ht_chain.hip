@@ -22,12 +22,17 @@
 //   1. the wavefront owning column i reduces its norm, forms the reflector
 //      (sign convention of LAPACK's dlarfg: beta = -sign(alpha) ||x||;
 //      columns outside [2^-450, 2^450] are scaled by an exact power of two
-//      first) and writes v to one of two LDS buffers;
+//      first) and writes v and the finished column of the factor (R or L)
+//      to one of two pairs of LDS buffers;
 //   2. one workgroup barrier;
 //   3. every wavefront reads v for its rows, forms the four column dots,
-//      reduces them and applies the rank-1 update.
+//      reduces them and applies the rank-1 update; each wavefront also
+//      stores 16 rows of v and of the factor column to global memory, so
+//      the owner's next reflector does not wait behind those stores.
 // The owner of column i+1 proceeds to step 1 of the next reflector as soon as
-// its own update is done; the double buffer makes the single barrier enough.
+// its own update is done; the double buffers make the single barrier enough.
+// v sits in LDS with lane rl's RQ rows strided by 32 (entry q of lane rl at
+// q * 32 + rl), so the reads of a wavefront hit consecutive banks.
 #include "ht_device.h"
 #include "ht_internal.h"
 
@@ -107,8 +112,10 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(ChainJobs jobs) {
   double* __restrict__ Wout = jb.W;
   constexpr int RQ = 2 * KMAX / 32;  // rows per lane
   constexpr int CJ = 4;              // columns per lane
-  __shared__ double vbuf[2][2 * KMAX];
+  __shared__ double vbuf[2][2 * KMAX];  // v, strided layout (vslot)
+  __shared__ double rbuf[2][2 * KMAX];  // the factor column, by row
   __shared__ double tbuf[2];
+  auto vslot = [](int r) { return (r % RQ) * 32 + r / RQ; };
 
   const int tid = threadIdx.x;
   const int wv = tid >> 6, lane = tid & 63;
@@ -172,17 +179,14 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(ChainJobs jobs) {
     rf.beta = rf0.beta / sc;
     if (h == hi) {
       double* vb = vbuf[step & 1];
+      double* rb = rbuf[step & 1];
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
         const int r = rbase + q;
         const bool inx = r >= x0 && r < x1;
-        const double v = (r == p) ? 1.0 : (inx ? x[q] * rf.scal : 0.0);
-        vb[r] = v;
-        if (r < w) {
-          // column i of the factor (R or L) and reflector `step`
-          X[tidx(r, i, ldx, trans)] = (r == p) ? rf.beta : (inx ? 0.0 : x[q]);
-          Vout[(size_t)r + (size_t)step * ldo] = v;
-        }
+        vb[vslot(r)] = (r == p) ? 1.0 : (inx ? x[q] * rf.scal : 0.0);
+        // column i of the factor (R or L)
+        rb[r] = (r == p) ? rf.beta : (inx ? 0.0 : x[q]);
       }
       if (rl == 0) tbuf[step & 1] = rf.tau;
     }
@@ -196,7 +200,15 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(ChainJobs jobs) {
     const double tau = tbuf[step & 1];
     double v[RQ];
 #pragma unroll
-    for (int q = 0; q < RQ; ++q) v[q] = vbuf[step & 1][rbase + q];
+    for (int q = 0; q < RQ; ++q) v[q] = vbuf[step & 1][vslot(rbase + q)];
+    {
+      // reflector `step` and column i of the factor: 16 rows per wavefront
+      const int r = 16 * wv + (lane & 15);
+      if (lane < 32 && r < w) {
+        if (lane < 16) Vout[(size_t)r + (size_t)step * ldo] = vbuf[step & 1][vslot(r)];
+        else X[tidx(r, i, ldx, trans)] = rbuf[step & 1][r];
+      }
+    }
     double d[CJ];
 #pragma unroll
     for (int j = 0; j < CJ; ++j) {

@@ -250,8 +250,54 @@ struct Ctx {
   ht_options opt;
   int* host_ints;  // pinned mirror of w->ints
   Prof prof;
+  // side stream: the sweeps of a chain's windows run there while the chain
+  // itself (one workgroup per window) goes on in `st`; null = one stream
+  hipStream_t st2 = nullptr;
+  std::vector<hipEvent_t> evs;
+  size_t evused = 0;
+  bool ev_failed = false;
+  hipEvent_t ev() {
+    if (evused == evs.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        ev_failed = true;
+        return nullptr;
+      }
+      evs.push_back(e);
+    }
+    return evs[evused++];
+  }
+  // make `to` wait for the work enqueued so far on `from`
+  void order(hipStream_t from, hipStream_t to) {
+    hipEvent_t e = ev();
+    if (!e) {  // cannot order by events: wait on the host instead
+      (void)hipStreamSynchronize(from);
+      return;
+    }
+    (void)hipEventRecord(e, from);
+    (void)hipStreamWaitEvent(to, e, 0);
+  }
   double flops = 0.0;
   int64_t cols_extra_ir = 0, ir_steps = 0, ir_failures = 0, absorptions = 0, columns = 0;
+};
+
+// While alive, the launch helpers enqueue on the side stream and use Wk as
+// their product buffer (n x nb: enough for the window products, P = X V or
+// V^T X with at most nb reflectors; the main stream keeps P for its own
+// products, and Wk is not used by the main stream while chain sweeps run on
+// the side).
+struct OnSide {
+  Ctx& c;
+  hipStream_t st0;
+  double* P0;
+  explicit OnSide(Ctx& c_) : c(c_), st0(c_.st), P0(c_.w->P) {
+    c.st = c.st2;
+    c.w->P = c.w->Wk;
+  }
+  ~OnSide() {
+    c.st = st0;
+    c.w->P = P0;
+  }
 };
 
 // A product of the WY updates (the absorption's window applications and
@@ -522,8 +568,29 @@ void absorb(Ctx& c, int s, int k) {
   // factored in one launch on two workgroups.
   double* V2 = w.V + k;
   copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
+
+  // (3.3.1 c, d, e) right absorption.  B, Z and rows 0..s of A:
+  //   X(:, j+1:n) <- X Q^;  W = X(:, s+1:j+1) V1 + X(:, n-k:n) L1;
+  //   X(:, s+1:j+1) -= W T V1^T;  X(:, n-k:n) -= W T L1^T.
+  struct RT { double* X; int ld; int rows; bool tri; };
+  std::vector<RT> rts;
+  rts.push_back({B, ldb, n, true});
+  if (c.wantZ) rts.push_back({c.Z, c.ldz, n, false});
+  rts.push_back({A, lda, s + 1, false});
+  std::vector<RJob> rjobs;
+  for (auto& rt : rts) rjobs.push_back(RJob{rt.X, rt.ld, rt.rows, rt.tri, 0});
+  rjobs.push_back(RJob{at(A, lda, s + 1, 0), lda, L, false, s + 1});
   {
     const std::vector<Win> r0 = right_windows(bl, 0), l2 = left_windows(bl, 2);
+    // The sweep runs in chunks of windows, each as soon as the chain has
+    // factored them; with a side stream the chunks run there while the chain
+    // goes on (the chain touches only V2, the copy of U2 and its transform
+    // slots, the sweep only B, Z, A).  The chunks are the same with and
+    // without the side stream, so the results are bitwise the same.
+    const bool side = c.st2 != nullptr;
+    const size_t chunk = std::max<size_t>(8, r0.size() / 12);
+    size_t swept = 0;
+    if (side) c.order(c.st, c.st2);
     for (size_t t = 0; t < r0.size(); ++t) {
       const Win &a = r0[t], &b = l2[t];
       ChainJobs jobs;
@@ -535,27 +602,25 @@ void absorb(Ctx& c, int s, int k) {
       const double fl = 4.0 * (a.wdt + b.wdt) * (double)k * k;
       c.prof.end(c.st, pi, fl);
       c.flops += fl;
+      if (t + 1 - swept >= chunk || t + 1 == r0.size()) {
+        const std::vector<Win> part(r0.begin() + swept, r0.begin() + t + 1);
+        if (side) {
+          c.order(c.st, c.st2);
+          OnSide os(c);
+          sweep_jobs(c, rjobs, j, bl, 0, part);
+        } else {
+          sweep_jobs(c, rjobs, j, bl, 0, part);
+        }
+        swept = t + 1;
+      }
     }
+    if (side) c.order(c.st2, c.st);
   }
   const double* L1 = w.V + (L - k);
   const double* V1 = w.V;
   copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
   copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
 
-  // (3.3.1 c, d, e) right absorption.  B, Z and rows 0..s of A:
-  //   X(:, j+1:n) <- X Q^;  W = X(:, s+1:j+1) V1 + X(:, n-k:n) L1;
-  //   X(:, s+1:j+1) -= W T V1^T;  X(:, n-k:n) -= W T L1^T.
-  struct RT { double* X; int ld; int rows; bool tri; };
-  std::vector<RT> rts;
-  rts.push_back({B, ldb, n, true});
-  if (c.wantZ) rts.push_back({c.Z, c.ldz, n, false});
-  rts.push_back({A, lda, s + 1, false});
-  {
-    std::vector<RJob> jobs;
-    for (auto& rt : rts) jobs.push_back(RJob{rt.X, rt.ld, rt.rows, rt.tri, 0});
-    jobs.push_back(RJob{at(A, lda, s + 1, 0), lda, L, false, s + 1});
-    sweep_jobs(c, jobs, j, bl, 0, right_windows(bl, 0));
-  }
   for (auto& rt : rts) {
     if (rt.rows <= 0) continue;
     double* Xs = at(rt.X, rt.ld, 0, s + 1);
@@ -973,7 +1038,22 @@ int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t l
   c.opt = o;
   c.host_ints = hints;
   c.prof.on = (o.flags & HT_FLAG_PROFILE) != 0 && stats != nullptr;
+  // The side stream for the chain sweeps: not for small orders, not when
+  // every launch is timed on one stream, never in the no-allocation form.
+  // Non-blocking, so that it runs beside the caller's stream even when that
+  // is the null stream; the two are ordered by events only.
+  if (!noalloc && !c.prof.on && !(o.flags & HT_FLAG_ONE_STREAM) && ni > 256) {
+    if (hipStreamCreateWithFlags(&c.st2, hipStreamNonBlocking) != hipSuccess) c.st2 = nullptr;
+  }
   rc = run(c);
+  if (c.st2) {
+    c.order(c.st2, st);
+    (void)hipStreamDestroy(c.st2);
+    c.st2 = nullptr;
+  }
+  if (c.ev_failed && rc == 0) rc = HT_ERR_HIP;
+  for (hipEvent_t e : c.evs) (void)hipEventDestroy(e);
+  c.evs.clear();
   const hipError_t le = hipGetLastError();
   if (rc == 0 && le != hipSuccess) { g_last_hip = le; rc = HT_ERR_HIP; }
   if (stats || owned) (void)hipStreamSynchronize(st);
