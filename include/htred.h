@@ -106,12 +106,6 @@ typedef struct {
 #define HT_FLAG_PROFILE      2  /* time kernel classes with HIP events (stats) */
 #define HT_FLAG_SOLVE_SOLO   4  /* triangular solves on one workgroup, without
                                    helper workgroups (slower; for testing) */
-#define HT_FLAG_ONE_STREAM   8  /* ht_reduce: enqueue everything on `stream`.  By
-                                   default (n > 256, no HT_FLAG_PROFILE) the sweeps of
-                                   a chain's windows run on a second (non-blocking)
-                                   stream that the call creates, while the chain
-                                   itself goes on; the results are bitwise the same
-                                   either way */
 
 /* Kernel classes reported in ht_stats.prof_* when HT_FLAG_PROFILE is set.
  * prof_work is the algorithmic work of the class: flops for the
@@ -177,10 +171,12 @@ size_t ht_workspace_size(int64_t n, const ht_options *opt);
  * B triangular) is carried along; with HT_QZ_NONE they are not touched.
  * Leading dimensions must also be <= INT32_MAX (-6..-9 otherwise).
  *
- * The call synchronises `stream` once per reflector pair and once per
- * iterative-refinement step to read the refinement verdict, through a
- * 256-byte pinned host buffer that the call allocates and frees itself, so
- * it is not graph-capturable (ht_reduce_batched is).  The call keeps no
+ * The host reads each panel column's refinement verdict (Sec. 3.2.2 c)
+ * through a 256-byte pinned host buffer that the call allocates and frees
+ * itself, one column late: the next column is already enqueued, and is
+ * rolled back and redone when the verdict asks for refinement.  So the call
+ * waits for `stream` about once per reflector pair and per refinement step
+ * and is not graph-capturable (ht_reduce_batched is).  The call keeps no
  * state between calls: concurrent calls from several host threads on
  * different streams (with different workspaces) are independent.
  * HT_FLAG_CHECK_FINITE uses a word at the end of the caller's workspace, or
@@ -249,7 +245,7 @@ int ht_preprocess(double *A, double *B, double *Q, double *Z, int64_t n, int64_t
  * HT_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library, one per GPU, held
  * until the process ends.  Orders whose workspace (ht_workspace_size for
  * the same options) exceeds it return HT_ERR_TOO_LARGE: it holds orders up
- * to 2250 at nb = 128, 4993 at nb = 64 and 9993 at nb = 32.
+ * to 2248 at nb = 128, 4984 at nb = 64 and 9958 at nb = 32.
  * The call allocates nothing: refinement verdicts are read into pageable
  * host memory of the call, HT_FLAG_CHECK_FINITE uses a word of the array,
  * and HT_FLAG_PROFILE (which creates HIP events) returns HT_ERR_UNSUPPORTED.

@@ -207,14 +207,23 @@ __global__ __launch_bounds__(256) void k_gemv_n_small(int m, int k, double alpha
   const int row = blockIdx.x * 256 + threadIdx.x;
   if (row >= m) return;
   const double* p = X + row;
-  double s0 = 0.0, s1 = 0.0;
+  // sixteen loads in flight per lane, four partial sums
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int c = 0;
-  for (; c + 2 <= k; c += 2) {
-    s0 = fma(p[(size_t)c * ldx], xs[c], s0);
-    s1 = fma(p[(size_t)(c + 1) * ldx], xs[c + 1], s1);
+  for (; c + 16 <= k; c += 16) {
+    double a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] = p[(size_t)(c + u) * ldx];
+#pragma unroll
+    for (int u = 0; u < 16; u += 4) {
+      s0 = fma(a[u], xs[c + u], s0);
+      s1 = fma(a[u + 1], xs[c + u + 1], s1);
+      s2 = fma(a[u + 2], xs[c + u + 2], s2);
+      s3 = fma(a[u + 3], xs[c + u + 3], s3);
+    }
   }
-  if (c < k) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
-  const double s = s0 + s1;
+  for (; c < k; ++c) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+  const double s = (s0 + s1) + (s2 + s3);
   y[row] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[row]);
 }
 
@@ -238,17 +247,27 @@ __global__ __launch_bounds__(256) void k_gemv_part(int m, int k, const double* _
   constexpr int CW = KC / 4;
   int cs = wave * CW, ce = min(kc, cs + CW);
   if (TRI) cs = max(cs, row - c0);
-  double s0 = 0.0, s1 = 0.0;
+  // sixteen loads in flight per lane (four partial sums), so that a wave
+  // keeps enough bytes outstanding to stream X at the HBM rate
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (row < m) {
     const double* p = X + (size_t)row + (size_t)c0 * ldx;
     int c = cs;
-    for (; c + 2 <= ce; c += 2) {
-      s0 = fma(p[(size_t)c * ldx], xs[c], s0);
-      s1 = fma(p[(size_t)(c + 1) * ldx], xs[c + 1], s1);
+    for (; c + 16 <= ce; c += 16) {
+      double a[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) a[u] = p[(size_t)(c + u) * ldx];
+#pragma unroll
+      for (int u = 0; u < 16; u += 4) {
+        s0 = fma(a[u], xs[c + u], s0);
+        s1 = fma(a[u + 1], xs[c + u + 1], s1);
+        s2 = fma(a[u + 2], xs[c + u + 2], s2);
+        s3 = fma(a[u + 3], xs[c + u + 3], s3);
+      }
     }
-    if (c < ce) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
+    for (; c < ce; ++c) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
   }
-  red[wave][lane] = s0 + s1;
+  red[wave][lane] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   if (wave == 0 && row < m)
     part[(size_t)blockIdx.y * m + row] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
@@ -303,9 +322,19 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(int m, int k, const double*
   const int r0 = blockIdx.y * RC;
   const int r1 = min(m, r0 + RC);
   const double* p = X + (size_t)c * ldx;
-  double s = 0.0;
-  for (int r = r0 + threadIdx.x; r < r1; r += 256) s = fma(p[r], x[r], s);
-  s = block_sum(s, sh);
+  // four rows per thread in flight, four partial sums
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int r = r0 + threadIdx.x;
+  for (; r + 768 < r1; r += 1024) {
+    const double a0 = p[r], a1 = p[r + 256], a2 = p[r + 512], a3 = p[r + 768];
+    const double b0 = x[r], b1 = x[r + 256], b2 = x[r + 512], b3 = x[r + 768];
+    s0 = fma(a0, b0, s0);
+    s1 = fma(a1, b1, s1);
+    s2 = fma(a2, b2, s2);
+    s3 = fma(a3, b3, s3);
+  }
+  for (; r < r1; r += 256) s0 = fma(p[r], x[r], s0);
+  double s = block_sum((s0 + s1) + (s2 + s3), sh);
   if (threadIdx.x == 0) {
     if (direct) z[c] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * z[c]);
     else part[(size_t)blockIdx.y * k + c] = s;
@@ -338,6 +367,80 @@ void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
 }
 
 // ---------------------------------------------------------------------------
+// Block-reflector application to one vector, the step that the panel of
+// Sec. 3.2.2 repeats for every column (the column update, the factored
+// solve's two factors and the residual's two factors):
+//   xu(0:mu) += alpha U(0:mu, 0:k) op(S) (U(d0:d0+md, 0:k)^T xd)
+// in two launches: the column sums U^T xd (k_gemv_t_part, partial sums per
+// chunk of rows), then k_wy_apply, whose every workgroup adds the partial
+// sums in chunk order, multiplies by the k x k triangular op(S) and updates
+// its 256 rows of xu.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_wy_apply(int mu, int k, int nch,
+                                                  const double* __restrict__ part,
+                                                  const double* __restrict__ S, int lds,
+                                                  int transS, double alpha,
+                                                  const double* __restrict__ U, int ldu,
+                                                  double* __restrict__ xu) {
+  __shared__ double zs[128], ys[128];
+  const int t = threadIdx.x;
+  if (t < k) {
+    double s = 0.0;
+    for (int c = 0; c < nch; ++c) s += part[(size_t)c * k + t];
+    zs[t] = s;
+  }
+  __syncthreads();
+  if (t < k) {
+    double s = 0.0;
+    if (!transS) {
+      for (int c = t; c < k; ++c) s = fma(S[t + (size_t)c * lds], zs[c], s);
+    } else {
+      for (int c = 0; c <= t; ++c) s = fma(S[c + (size_t)t * lds], zs[c], s);
+    }
+    ys[t] = s;
+  }
+  __syncthreads();
+  const int row = blockIdx.x * 256 + t;
+  if (row >= mu) return;
+  const double* p = U + row;
+  // sixteen loads in flight per lane, four partial sums
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = 0;
+  for (; c + 16 <= k; c += 16) {
+    double a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] = p[(size_t)(c + u) * ldu];
+#pragma unroll
+    for (int u = 0; u < 16; u += 4) {
+      s0 = fma(a[u], ys[c + u], s0);
+      s1 = fma(a[u + 1], ys[c + u + 1], s1);
+      s2 = fma(a[u + 2], ys[c + u + 2], s2);
+      s3 = fma(a[u + 3], ys[c + u + 3], s3);
+    }
+  }
+  for (; c < k; ++c) s0 = fma(p[(size_t)c * ldu], ys[c], s0);
+  xu[row] = fma(alpha, (s0 + s1) + (s2 + s3), xu[row]);
+}
+
+void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const double* U,
+              int ldu, const double* S, int lds, bool transS, const double* xd, double* xu,
+              double* z, double* partials) {
+  if (k <= 0 || mu <= 0) return;
+  const int nch = md > 0 ? cdiv(md, RC) : 0;
+  const double* src = partials;
+  if (nch == 1) {
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(k, 1), dim3(256), 0, st, md, k, U + d0, ldu, xd,
+                       partials, 1, 1.0, 0.0, z);
+    src = z;
+  } else if (nch > 1) {
+    hipLaunchKernelGGL(k_gemv_t_part, dim3(k, nch), dim3(256), 0, st, md, k, U + d0, ldu, xd,
+                       partials, 0, 1.0, 0.0, z);
+  }
+  hipLaunchKernelGGL(k_wy_apply, dim3(cdiv(mu, 256)), dim3(256), 0, st, mu, k, nch, src, S, lds,
+                     transS ? 1 : 0, alpha, U, ldu, xu);
+}
+
+// ---------------------------------------------------------------------------
 // Elementwise helpers.
 // ---------------------------------------------------------------------------
 __global__ void k_fill(double* x, int m, double v) {
@@ -346,6 +449,26 @@ __global__ void k_fill(double* x, int m, double v) {
 }
 void fill(hipStream_t st, double* x, int m, double v) {
   if (m > 0) hipLaunchKernelGGL(k_fill, dim3(cdiv(m, 256)), dim3(256), 0, st, x, m, v);
+}
+
+// x(0:m) = e_idx (idx in 0..m-1)
+__global__ void k_unit(double* x, int m, int idx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] = (i == idx) ? 1.0 : 0.0;
+}
+void unit_vec(hipStream_t st, double* x, int m, int idx) {
+  if (m > 0) hipLaunchKernelGGL(k_unit, dim3(cdiv(m, 256)), dim3(256), 0, st, x, m, idx);
+}
+
+// x(0:z) = 0, x(z:z+m) = src(0:m)
+__global__ void k_pad_copy(double* x, int z, const double* src, int m) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < z) x[i] = 0.0;
+  else if (i < z + m) x[i] = src[i - z];
+}
+void pad_copy(hipStream_t st, double* x, int z, const double* src, int m) {
+  if (z + m > 0)
+    hipLaunchKernelGGL(k_pad_copy, dim3(cdiv(z + m, 256)), dim3(256), 0, st, x, z, src, m);
 }
 
 __global__ void k_copy(double* d, const double* s, int m) {

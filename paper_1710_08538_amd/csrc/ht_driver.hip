@@ -65,13 +65,16 @@ struct Work {
   int n = 0, nb = 0;
   double *U, *V, *Y, *S, *T, *Ucp;
   double *acol_save, *ctil, *ysol, *dsol, *wv, *w2, *rv;
+  double *acol_save2, *ysol2, *rv2;  // the same for odd columns (speculation)
   double *tk, *tk2, *gk, *Ucat, *Kt, *Kt2, *P, *Wk;
   double* partials;
   double* kpart;       // split-contraction sums of the WY products
   double* pool[4][2];  // chain transform pools: [chain][V or W]
   double* Gws;
   double* dscal;       // [0] tau_u, [1] beta_u, [2] normB, [3..4] IR norms, [5] tau_v, [6] beta_v
-  int *flags, *ints;  // ints: [1] E_rhs, [2] E_corr, [3] status, [4] fixes, [5] scaled
+  // ints: [1] E_rhs, [2] E_corr, [3] status, [4] fixes, [5] scaled; [9], [11]
+  // E_rhs and status of odd columns
+  int *flags, *ints;
   int epoch = 0;
 };
 
@@ -97,6 +100,9 @@ size_t layout(Work* w, int n, int nb, char* base) {
   w->S = take(K * K);
   w->T = take(K * K);
   w->acol_save = take(N);
+  w->acol_save2 = take(N);
+  w->ysol2 = take(N);
+  w->rv2 = take(N);
   w->ctil = take(N);
   w->ysol = take(N);
   w->dsol = take(N);
@@ -121,6 +127,19 @@ size_t layout(Work* w, int n, int nb, char* base) {
   w->flags = (int*)take(trsv_flag_bytes((int)N) / 8 + 1);
   w->ints = (int*)take(32);
   return off;
+}
+
+// The refinement state of a panel column lives in one of two sets, by the
+// parity of the column, so that the next column can be started before this
+// one's verdict is known (see run()).
+struct ColBufs {
+  double *save, *ysol, *rv;
+  int *Erhs, *status;
+};
+ColBufs colbufs(Work& w, int kk) {
+  const int p = kk & 1;
+  return ColBufs{p ? w.acol_save2 : w.acol_save, p ? w.ysol2 : w.ysol, p ? w.rv2 : w.rv,
+                 w.ints + 1 + 8 * p, w.ints + 3 + 8 * p};
 }
 
 // Window list of a chain: (start, width, nrefl, slot, roff) in application
@@ -250,54 +269,10 @@ struct Ctx {
   ht_options opt;
   int* host_ints;  // pinned mirror of w->ints
   Prof prof;
-  // side stream: the sweeps of a chain's windows run there while the chain
-  // itself (one workgroup per window) goes on in `st`; null = one stream
-  hipStream_t st2 = nullptr;
-  std::vector<hipEvent_t> evs;
-  size_t evused = 0;
-  bool ev_failed = false;
-  hipEvent_t ev() {
-    if (evused == evs.size()) {
-      hipEvent_t e = nullptr;
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-        ev_failed = true;
-        return nullptr;
-      }
-      evs.push_back(e);
-    }
-    return evs[evused++];
-  }
-  // make `to` wait for the work enqueued so far on `from`
-  void order(hipStream_t from, hipStream_t to) {
-    hipEvent_t e = ev();
-    if (!e) {  // cannot order by events: wait on the host instead
-      (void)hipStreamSynchronize(from);
-      return;
-    }
-    (void)hipEventRecord(e, from);
-    (void)hipStreamWaitEvent(to, e, 0);
-  }
+  hipEvent_t status_ev[2] = {nullptr, nullptr};  // see post_status
+
   double flops = 0.0;
   int64_t cols_extra_ir = 0, ir_steps = 0, ir_failures = 0, absorptions = 0, columns = 0;
-};
-
-// While alive, the launch helpers enqueue on the side stream and use Wk as
-// their product buffer (n x nb: enough for the window products, P = X V or
-// V^T X with at most nb reflectors; the main stream keeps P for its own
-// products, and Wk is not used by the main stream while chain sweeps run on
-// the side).
-struct OnSide {
-  Ctx& c;
-  hipStream_t st0;
-  double* P0;
-  explicit OnSide(Ctx& c_) : c(c_), st0(c_.st), P0(c_.w->P) {
-    c.st = c.st2;
-    c.w->P = c.w->Wk;
-  }
-  ~OnSide() {
-    c.st = st0;
-    c.w->P = P0;
-  }
 };
 
 // A product of the WY updates (the absorption's window applications and
@@ -490,10 +465,24 @@ void chain(Ctx& c, int mode, bool trans, int wdt, int k, double* tile, int ld, d
   c.flops += 4.0 * wdt * (double)k * k;
 }
 
-int sync_status(Ctx& c) {
-  (void)hipMemcpyAsync(c.host_ints, c.w->ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c.st);
-  (void)hipStreamSynchronize(c.st);
-  return c.host_ints[3];
+// The refinement verdict of a column: copied to host memory behind the
+// work enqueued so far (post_status), read when needed (read_status).  With
+// an event per parity the host waits only for that copy, so the work
+// enqueued after it keeps the GPU busy meanwhile.
+void post_status(Ctx& c, const ColBufs& cb, int kk) {
+  const int p = kk & 1;
+  (void)hipMemcpyAsync(c.host_ints + 16 + p, cb.status, sizeof(int), hipMemcpyDeviceToHost, c.st);
+  if (c.status_ev[p]) (void)hipEventRecord(c.status_ev[p], c.st);
+}
+int read_status(Ctx& c, int kk) {
+  const int p = kk & 1;
+  if (c.status_ev[p]) (void)hipEventSynchronize(c.status_ev[p]);
+  else (void)hipStreamSynchronize(c.st);
+  return c.host_ints[16 + p];
+}
+int sync_status(Ctx& c, const ColBufs& cb, int kk) {
+  post_status(c, cb, kk);
+  return read_status(c, kk);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,9 +492,7 @@ int sync_status(Ctx& c) {
 void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, int* Eout) {
   Work& w = *c.w;
   const int L = c.n - s - 1, n = c.n;
-  gemv_t(c.st, L, nu, 1.0, w.U, n, ctil, 0.0, w.tk, w.partials);
-  trmv_small(c.st, false, nu, w.S, c.nb, w.tk, 1.0, w.tk2);
-  gemv_n(c.st, L, nu, -1.0, w.U, n, w.tk2, 1, 1.0, ctil, w.partials);
+  wy_apply(c.st, L, L, 0, nu, -1.0, w.U, n, w.S, c.nb, false, ctil, ctil, w.tk, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRSV);
   trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout,
@@ -513,32 +500,25 @@ void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, i
   c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
   hipLaunchKernelGGL(k_count_scaled, dim3(1), dim3(1), 0, c.st, Eout, w.ints + 5);
   if (kk > 0) {
-    gemv_t(c.st, L, kk, 1.0, w.V, n, ysol, 0.0, w.tk, w.partials);
-    trmv_small(c.st, true, kk, w.T, c.nb, w.tk, 1.0, w.tk2);
-    gemv_n(c.st, L, kk, -1.0, w.V, n, w.tk2, 1, 1.0, ysol, w.partials);
+    wy_apply(c.st, L, L, 0, kk, -1.0, w.V, n, w.T, c.nb, true, ysol, ysol, w.tk, w.partials);
   }
   c.flops += 1.0 * L * (double)L + 4.0 * L * (double)(nu + kk);
 }
 
 // Residual (Sec. 3.2.2 c): w = (I - V T V^T)[0; x]; w = B w;
 // w = (I - U S^T U^T) w; r = 2^{-E} rhs - w(kk:), rhs = e1 if NULL.
-void residual(Ctx& c, int s, int kk, const double* x, const double* rhs) {
+void residual(Ctx& c, int s, int kk, const double* x, const double* rhs, const ColBufs& cb) {
   Work& w = *c.w;
   const int L = c.n - s - 1, n = c.n, m = L - kk;
-  fill(c.st, w.wv, kk, 0.0);
-  copy(c.st, w.wv + kk, x, m);
-  gemv_t(c.st, m, kk, 1.0, w.V + kk, n, x, 0.0, w.tk, w.partials);
-  trmv_small(c.st, false, kk, w.T, c.nb, w.tk, 1.0, w.tk2);
-  gemv_n(c.st, L, kk, -1.0, w.V, n, w.tk2, 1, 1.0, w.wv, w.partials);
+  pad_copy(c.st, w.wv, kk, x, m);
+  wy_apply(c.st, L, m, kk, kk, -1.0, w.V, n, w.T, c.nb, false, x, w.wv, w.tk, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRMV);
   trmv_upper(c.st, L, Bp, c.ldb, w.wv, w.w2, w.partials);
   c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
-  gemv_t(c.st, L, kk + 1, 1.0, w.U, n, w.w2, 0.0, w.tk, w.partials);
-  trmv_small(c.st, true, kk + 1, w.S, c.nb, w.tk, 1.0, w.tk2);
-  gemv_n(c.st, L, kk + 1, -1.0, w.U, n, w.tk2, 1, 1.0, w.w2, w.partials);
-  ir_residual(c.st, m, w.w2 + kk, rhs, w.ints + 1, w.rv, x, w.dscal + 2, c.opt.ir_tol_factor,
-              w.ints + 3, w.dscal + 3);
+  wy_apply(c.st, L, L, 0, kk + 1, -1.0, w.U, n, w.S, c.nb, true, w.w2, w.w2, w.tk, w.partials);
+  ir_residual(c.st, m, w.w2 + kk, rhs, cb.Erhs, cb.rv, x, w.dscal + 2, c.opt.ir_tol_factor,
+              cb.status, w.dscal + 3);
   c.flops += 1.0 * L * (double)L + 4.0 * L * (double)(2 * kk + 1);
 }
 
@@ -582,15 +562,6 @@ void absorb(Ctx& c, int s, int k) {
   rjobs.push_back(RJob{at(A, lda, s + 1, 0), lda, L, false, s + 1});
   {
     const std::vector<Win> r0 = right_windows(bl, 0), l2 = left_windows(bl, 2);
-    // The sweep runs in chunks of windows, each as soon as the chain has
-    // factored them; with a side stream the chunks run there while the chain
-    // goes on (the chain touches only V2, the copy of U2 and its transform
-    // slots, the sweep only B, Z, A).  The chunks are the same with and
-    // without the side stream, so the results are bitwise the same.
-    const bool side = c.st2 != nullptr;
-    const size_t chunk = std::max<size_t>(8, r0.size() / 12);
-    size_t swept = 0;
-    if (side) c.order(c.st, c.st2);
     for (size_t t = 0; t < r0.size(); ++t) {
       const Win &a = r0[t], &b = l2[t];
       ChainJobs jobs;
@@ -602,19 +573,8 @@ void absorb(Ctx& c, int s, int k) {
       const double fl = 4.0 * (a.wdt + b.wdt) * (double)k * k;
       c.prof.end(c.st, pi, fl);
       c.flops += fl;
-      if (t + 1 - swept >= chunk || t + 1 == r0.size()) {
-        const std::vector<Win> part(r0.begin() + swept, r0.begin() + t + 1);
-        if (side) {
-          c.order(c.st, c.st2);
-          OnSide os(c);
-          sweep_jobs(c, rjobs, j, bl, 0, part);
-        } else {
-          sweep_jobs(c, rjobs, j, bl, 0, part);
-        }
-        swept = t + 1;
-      }
     }
-    if (side) c.order(c.st2, c.st);
+    sweep_jobs(c, rjobs, j, bl, 0, r0);
   }
   const double* L1 = w.V + (L - k);
   const double* V1 = w.V;
@@ -778,57 +738,11 @@ int run(Ctx& c) {
     zero_mat(st, w.V, L, nb, n);
     zero_mat(st, w.S, nb, nb, nb);
     zero_mat(st, w.T, nb, nb, nb);
-    int k = 0;
-    for (int kk = 0; kk < kmax; ++kk) {
-      const int j = s + kk;
-      double* acol = at(c.A, c.lda, s + 1, j);
-      copy(st, w.acol_save, acol, L);
-      // (a) update column j with the kk pending reflector pairs
-      if (kk > 0) {
-        gemv_n(st, L, kk, -1.0, w.Y, n, w.V + (kk - 1), n, 1.0, acol, w.partials);
-        gemv_t(st, L, kk, 1.0, w.U, n, acol, 0.0, w.tk, w.partials);
-        trmv_small(st, true, kk, w.S, nb, w.tk, 1.0, w.tk2);
-        gemv_n(st, L, kk, -1.0, w.U, n, w.tk2, 1, 1.0, acol, w.partials);
-        c.flops += 6.0 * L * (double)kk;
-      }
-      // (b) left reflector on A(j+1:n, j); extend S
-      const int m = L - kk;
-      double* ucol = at(w.U, n, kk, kk);
-      house(st, m, acol + kk, ucol, w.dscal + 0, w.dscal + 1, true);
-      if (kk > 0) gemv_t(st, m, kk, 1.0, w.U + kk, n, ucol, 0.0, w.tk, w.partials);
-      wy_append(st, w.S, nb, kk, w.tk, w.dscal + 0);
-      // (c) solve B~22 x = e1 via the enlarged system
-      //   ctil = (I - U S U^T) e_kk  (computed as e_kk then the update)
-      fill(st, w.ctil, L, 0.0);
-      hipLaunchKernelGGL(k_add_at, dim3(1), dim3(1), 0, st, w.ctil, kk, 1.0);
-      factored_solve(c, s, kk, kk + 1, w.ctil, w.ysol, w.ints + 1);
-      double* x = w.ysol + kk;
-      bool ok = true;
-      if (kk > 0) {
-        residual(c, s, kk, x, nullptr);
-        int status = sync_status(c);
-        int it = 0;
-        if (!status) c.cols_extra_ir++;
-        while (!status && it < c.opt.max_ir) {
-          // correction: solve B~22 d = r, x <- 2^{-E2} x + d
-          fill(st, w.ctil, kk, 0.0);
-          copy(st, w.ctil + kk, w.rv, m);
-          factored_solve(c, s, kk, kk + 1, w.ctil, w.dsol, w.ints + 2);
-          ir_update(st, m, x, w.dsol + kk, w.ints + 2, w.ints + 1);
-          residual(c, s, kk, x, nullptr);
-          status = sync_status(c);
-          ++it;
-          c.ir_steps++;
-        }
-        if (!status) ok = false;
-      }
-      if (!ok) {
-        // undo the left reflector: restore column j; U(:, kk), S(:, kk) are dropped
-        copy(st, acol, w.acol_save, L);
-        c.ir_failures++;
-        break;
-      }
-      // (d) right reflector on x; extend T and Y
+    // (d) of column kk: right reflector on x; extend T and Y
+    auto step_d = [&](int kk) {
+      const ColBufs cb = colbufs(w, kk);
+      const int j = s + kk, m = L - kk;
+      double* x = cb.ysol + kk;
       double* vcol = at(w.V, n, kk, kk);
       house(st, m, x, vcol, w.dscal + 5, w.dscal + 6, false);
       if (kk > 0) gemv_t(st, m, kk, 1.0, w.V + kk, n, vcol, 0.0, w.tk, w.partials);
@@ -841,8 +755,93 @@ int run(Ctx& c) {
       hipLaunchKernelGGL(k_scale_by, dim3((L + 255) / 256), dim3(256), 0, st, ycol, L,
                          w.dscal + 5);
       c.flops += 2.0 * L * (double)m + 4.0 * L * (double)kk;
-      k = kk + 1;
-      c.columns++;
+    };
+    // Column kk up to its first refinement verdict (posted, not read), then
+    // (d) on the assumption that no refinement is needed.
+    auto enqueue = [&](int kk) {
+      const ColBufs cb = colbufs(w, kk);
+      const int j = s + kk, m = L - kk;
+      double* acol = at(c.A, c.lda, s + 1, j);
+      copy(st, cb.save, acol, L);
+      // (a) update column j with the kk pending reflector pairs
+      if (kk > 0) {
+        gemv_n(st, L, kk, -1.0, w.Y, n, w.V + (kk - 1), n, 1.0, acol, w.partials);
+        wy_apply(st, L, L, 0, kk, -1.0, w.U, n, w.S, nb, true, acol, acol, w.tk, w.partials);
+        c.flops += 6.0 * L * (double)kk;
+      }
+      // (b) left reflector on A(j+1:n, j); extend S
+      double* ucol = at(w.U, n, kk, kk);
+      house(st, m, acol + kk, ucol, w.dscal + 0, w.dscal + 1, true);
+      if (kk > 0) gemv_t(st, m, kk, 1.0, w.U + kk, n, ucol, 0.0, w.tk, w.partials);
+      wy_append(st, w.S, nb, kk, w.tk, w.dscal + 0);
+      // (c) solve B~22 x = e1 via the enlarged system
+      //   ctil = (I - U S U^T) e_kk  (computed as e_kk then the update)
+      unit_vec(st, w.ctil, L, kk);
+      factored_solve(c, s, kk, kk + 1, w.ctil, cb.ysol, cb.Erhs);
+      if (kk > 0) {  // the first column of a panel is not refined (Sec. 2.3)
+        residual(c, s, kk, cb.ysol + kk, nullptr, cb);
+        post_status(c, cb, kk);
+      }
+      step_d(kk);
+    };
+    // Refinement of column kk after a failed first verdict: correction
+    // steps until the residual test passes or max_ir steps are spent.
+    auto refine = [&](int kk) -> bool {
+      const ColBufs cb = colbufs(w, kk);
+      const int m = L - kk;
+      double* x = cb.ysol + kk;
+      int status = 0;
+      for (int it = 0; !status && it < c.opt.max_ir; ++it) {
+        // correction: solve B~22 d = r, x <- 2^{-E2} x + d
+        pad_copy(st, w.ctil, kk, cb.rv, m);
+        factored_solve(c, s, kk, kk + 1, w.ctil, w.dsol, w.ints + 2);
+        ir_update(st, m, x, w.dsol + kk, w.ints + 2, cb.Erhs);
+        residual(c, s, kk, x, nullptr, cb);
+        status = sync_status(c, cb, kk);
+        c.ir_steps++;
+      }
+      return status != 0;
+    };
+
+    // The columns run one ahead of their verdicts: column kk is enqueued
+    // (including its (d)) before column kk-1's verdict is read, so the GPU
+    // is not idle while the host waits.  When column kk-1 needs refinement,
+    // column kk is rolled back (its column of A restored; everything else it
+    // wrote is rewritten when it runs again), column kk-1 is refined and its
+    // (d) redone, or, if refinement fails, undone as in Algorithm 1.  The
+    // work that stands is the same, in the same order, as without the
+    // speculation.
+    int k = 0;
+    int pending = -1;  // enqueued column whose verdict is not read yet
+    int kk = 0;
+    for (;;) {
+      const bool enq = kk < kmax;
+      if (enq) enqueue(kk);
+      if (pending >= 0) {
+        const int q = pending;
+        pending = -1;
+        if (q > 0 && !read_status(c, q)) {
+          if (enq) copy(st, at(c.A, c.lda, s + 1, s + kk), colbufs(w, kk).save, L);
+          c.cols_extra_ir++;
+          if (!refine(q)) {
+            // undo the left reflector: restore column s+q; U(:, q), S(:, q) are dropped
+            copy(st, at(c.A, c.lda, s + 1, s + q), colbufs(w, q).save, L);
+            c.ir_failures++;
+            k = q;
+            break;
+          }
+          step_d(q);
+          c.columns++;
+          if (enq) continue;  // column kk runs again
+        } else {
+          c.columns++;
+        }
+      }
+      if (!enq) {
+        k = kmax;
+        break;
+      }
+      pending = kk++;
     }
     if (k == 0) return HT_ERR_HIP;  // cannot happen: the first column never refines
     absorb(c, s, k);
@@ -1038,22 +1037,15 @@ int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t l
   c.opt = o;
   c.host_ints = hints;
   c.prof.on = (o.flags & HT_FLAG_PROFILE) != 0 && stats != nullptr;
-  // The side stream for the chain sweeps: not for small orders, not when
-  // every launch is timed on one stream, never in the no-allocation form.
-  // Non-blocking, so that it runs beside the caller's stream even when that
-  // is the null stream; the two are ordered by events only.
-  if (!noalloc && !c.prof.on && !(o.flags & HT_FLAG_ONE_STREAM) && ni > 256) {
-    if (hipStreamCreateWithFlags(&c.st2, hipStreamNonBlocking) != hipSuccess) c.st2 = nullptr;
-  }
+  // events that let the host wait for a posted verdict alone (not in the
+  // no-allocation form, which waits for the stream instead)
+  if (!noalloc)
+    for (int p = 0; p < 2; ++p)
+      if (hipEventCreateWithFlags(&c.status_ev[p], hipEventDisableTiming) != hipSuccess)
+        c.status_ev[p] = nullptr;
   rc = run(c);
-  if (c.st2) {
-    c.order(c.st2, st);
-    (void)hipStreamDestroy(c.st2);
-    c.st2 = nullptr;
-  }
-  if (c.ev_failed && rc == 0) rc = HT_ERR_HIP;
-  for (hipEvent_t e : c.evs) (void)hipEventDestroy(e);
-  c.evs.clear();
+  for (int p = 0; p < 2; ++p)
+    if (c.status_ev[p]) (void)hipEventDestroy(c.status_ev[p]);
   const hipError_t le = hipGetLastError();
   if (rc == 0 && le != hipSuccess) { g_last_hip = le; rc = HT_ERR_HIP; }
   if (stats || owned) (void)hipStreamSynchronize(st);

@@ -44,6 +44,14 @@ void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
 void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
             const double* x, double beta, double* z, double* partials);
 
+// xu(0:mu) += alpha U(0:mu, 0:k) op(S) (U(d0:d0+md, 0:k)^T xd) for an upper
+// triangular k x k S (k <= 128), op(S) = S^T when transS: two launches in
+// place of gemv_t + trmv_small + gemv_n.  z (k doubles) and partials are
+// scratch.
+void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const double* U,
+              int ldu, const double* S, int lds, bool transS, const double* xd, double* xu,
+              double* z, double* partials);
+
 // y = B * x for upper triangular B (m x m); y and x distinct; partials as gemv_n.
 void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x,
                 double* y, double* partials);
@@ -76,6 +84,8 @@ void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt,
 
 // Elementwise helpers.
 void fill(hipStream_t st, double* x, int m, double v);
+void unit_vec(hipStream_t st, double* x, int m, int idx);           // x = e_idx
+void pad_copy(hipStream_t st, double* x, int z, const double* src, int m);  // x = [0_z; src]
 void copy(hipStream_t st, double* dst, const double* src, int m);
 void copy_mat(hipStream_t st, int m, int n, const double* src, int lds, double* dst, int ldd);
 void set_identity(hipStream_t st, double* X, int n, int ld);

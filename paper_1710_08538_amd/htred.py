@@ -23,7 +23,6 @@ HT_FLAG_CHECK_FINITE = 1
 HT_NOALLOC_SCRATCH_BYTES = 64 << 20
 HT_FLAG_PROFILE = 2
 HT_FLAG_SOLVE_SOLO = 4
-HT_FLAG_ONE_STREAM = 8
 PROF_CLASSES = ("wy", "trsv", "trmv", "ygemv", "chain", "sweep")
 
 
@@ -162,7 +161,7 @@ def _qz(X, mode, n, like, name):
 
 
 def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, check_finite,
-                 profile, solve_solo, qmode, zmode, ilo=0, one_stream=False):
+                 profile, solve_solo, qmode, zmode, ilo=0):
     n = A.shape[0]
     lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
     Q, ldq = _qz(Q, qmode, n, A, "Q")
@@ -174,8 +173,7 @@ def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, ch
                 n_slices=n_slices, qmode=qmode, zmode=zmode, ilo=ilo,
                 flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
                 | (HT_FLAG_PROFILE if profile else 0)
-                | (HT_FLAG_SOLVE_SOLO if solve_solo else 0)
-                | (HT_FLAG_ONE_STREAM if one_stream else 0))
+                | (HT_FLAG_SOLVE_SOLO if solve_solo else 0))
     ptrs = (A.data_ptr(), B.data_ptr(), Q.data_ptr() if Q is not None else None,
             Z.data_ptr() if Z is not None else None, n, lda, ldb, ldq, ldz)
     return Q, Z, o, ptrs
@@ -184,7 +182,7 @@ def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, ch
 def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
            prec=HT_PREC_FP64, n_slices=0, stats=False, workspace=None, stream=None,
            check_finite=False, profile=False, solve_solo=False, qmode=HT_QZ_IDENTITY,
-           zmode=HT_QZ_IDENTITY, ilo=0, one_stream=False):
+           zmode=HT_QZ_IDENTITY, ilo=0):
     """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
 
     A, B: n x n column-major float64 GPU tensors (B upper triangular).
@@ -197,11 +195,9 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     solve_solo: run every triangular solve on one workgroup (testing).
     ilo: first column to reduce (columns before it already final, e.g. after
         preprocess()).
-    one_stream: keep every launch on `stream` (no side stream for sweeps).
     """
     Q, Z, o, ptrs = _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices,
-                                 check_finite, profile, solve_solo, qmode, zmode, ilo,
-                                 one_stream)
+                                 check_finite, profile, solve_solo, qmode, zmode, ilo)
     st = Stats()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:

@@ -93,12 +93,12 @@ def test_noalloc_argument_validation_without_device(L):
     from paper_1710_08538_amd import htred
     o = htred.options(nb=128)
     lim = htred.HT_NOALLOC_SCRATCH_BYTES
-    # the largest orders the header states: 2250 (nb 128), 4993 (64), 9993 (32)
-    for nb, nmax in ((128, 2250), (64, 4993), (32, 9993)):
+    # the largest orders the header states: 2248 (nb 128), 4984 (64), 9958 (32)
+    for nb, nmax in ((128, 2248), (64, 4984), (32, 9958)):
         ob = htred.options(nb=nb)
         assert L.ht_workspace_size(nmax, ctypes.byref(ob)) <= lim
         assert L.ht_workspace_size(nmax + 1, ctypes.byref(ob)) > lim
-    assert L.ht_reduce_noalloc(None, None, None, None, 2251, 2251, 2251, 2251, 2251,
+    assert L.ht_reduce_noalloc(None, None, None, None, 2249, 2249, 2249, 2249, 2249,
                                ctypes.byref(o), None, None) == htred.HT_ERR_TOO_LARGE
     assert L.ht_reduce_noalloc(None, None, None, None, -1, 1, 1, 1, 1, ctypes.byref(o), None,
                                None) == -5
