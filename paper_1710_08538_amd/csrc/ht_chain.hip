@@ -4,8 +4,10 @@
 // restoring it from the right (step e), QR when restoring it from the left
 // (step f).  RQ is done as QL of the transposed block.
 //
-// One workgroup factors one w x k tile (w <= 2 KMAX, k <= KMAX) held in
-// registers.  The orthogonal factor is returned in regular WY form
+// k_chain_reg: one workgroup factors one w x k tile (w <= 2 KMAX,
+// k <= KMAX) held in registers, one workgroup barrier per reflector;
+// k_chain_blk (further down) factors tiles of more than 64 columns in panels
+// of 16 with FP64 MFMA block updates.  The orthogonal factor is returned in regular WY form
 // Qf = I - V W^T (Sec. 2.4), reflectors in the order they are computed, so
 //   QR:  tile = Qf [R; 0],   QL:  tile = Qf [0; L].
 // W is accumulated alongside the factorisation:  with Qf_i = I - V_i W_i^T,
@@ -266,12 +268,301 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(ChainJobs jobs) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Blocked factorisation: panels of 16 columns, FP64 MFMA block updates.
+//
+// The tile is taken in its QR orientation: for QL the rows and columns are
+// reversed (logical row r = physical row w-1-r, logical column c = physical
+// column k-1-c), which turns the QL factorisation into a QR factorisation
+// with the same reflectors in the same order.  With Qf = I - V W^T after the
+// reflectors of panels 0..p-1, panel p (columns 16p..16p+15) is factored by
+// the wavefront that holds it, one reflector after the other as above (its
+// finished columns becoming columns of W and taking the panel's later
+// reflectors); the panel's factor is then Qp = I - Vp Wp^T, and every other
+// column, still to be reduced or already a column of W, takes Qp^T at once:
+//   C <- C - Wp (Vp^T C),
+// two 16-deep products on v_mfma_f64_16x16x4f64.  The result equals the
+// reflector-by-reflector scheme up to rounding (the same reflectors, the
+// same W).
+//
+// Layouts.  Eight wavefronts; wavefront wv holds logical columns 16wv ..
+// 16wv+15 in MFMA accumulator layout: lane l = 16g + c, register xt[t][i] =
+// row 16t + g + 4i of column 16wv + c, which is also the B-operand layout of
+// the k-chunks of a product over rows.  While it factors its panel, the
+// owning wavefront holds the panel in row layout instead, in the same
+// registers: xt[j][q] = row l + 64q of a panel column.  The pivot column is
+// always xt[0]: after each reflector the 16 columns rotate by one register
+// (sixteen rotations restore the order), so the reflector step is one loop
+// body rather than sixteen unrolled copies, which would not fit the
+// instruction cache.  Reflector sums over rows are reductions over the 64
+// lanes; the 16 column sums of a reflector step are reduce-scattered
+// (v_permlane32/16_swap, then DPP mirrors) so that lane 4j ends with the
+// sum of column j.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kBlkNT = 512;  // threads: eight wavefronts of 16 columns
+constexpr int kLP = 258;     // leading dimension of the panel and Vp in LDS
+constexpr int kLW = 272;     // leading dimension of -Wp in LDS
+
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d acc) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ void swap32(double& x, double& y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false,
+                                                   false);
+  x = __hiloint2double((int)hi[0], (int)lo[0]);
+  y = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Sum over all 64 lanes, in every lane.
+__device__ __forceinline__ double wave_total(double x) {
+  x = row_sum16(x);
+  double y = x;
+  swap16(x, y);
+  x += y;
+  y = x;
+  swap32(x, y);
+  return x + y;
+}
+__device__ __forceinline__ double wave_maxall(double x) {
+  x = row_max16(x);
+  double y = x;
+  swap16(x, y);
+  x = fmax(x, y);
+  y = x;
+  swap32(x, y);
+  return fmax(x, y);
+}
+
+// One reduce-scatter step inside 16-lane rows: lanes with `upper` set keep
+// b's sum, the others a's; the partner lane is given by the DPP control.
+template <int CTRL>
+__device__ __forceinline__ double rs_pair(double a, double b, bool upper) {
+  const double send = upper ? a : b;
+  const double keep = upper ? b : a;
+  return keep + dpp_d<CTRL>(send);
+}
+
+// d[0..15]: per-lane partial sums of 16 quantities.  Returns, in lane l, the
+// total over all lanes of quantity (l >> 2) & 15.
+__device__ __forceinline__ double reduce_scatter16(double (&d)[16], int lane) {
+  double u[8], w4[4], y2[2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double a = d[i], b = d[i + 8];
+    swap32(a, b);
+    u[i] = a + b;  // lanes 0-31: quantity i, lanes 32-63: i + 8
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double a = u[i], b = u[i + 4];
+    swap16(a, b);
+    w4[i] = a + b;  // even rows: u[i], odd rows: u[i + 4]
+  }
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) y2[i] = rs_pair<kDppMirror>(w4[i], w4[i + 2], b3);
+  double z = rs_pair<kDppHalfMirror>(y2[0], y2[1], b2);
+  z += dpp_d<kDppXor2>(z);
+  z += dpp_d<kDppXor1>(z);
+  return z;
+}
+
+struct BlkLds {
+  double pw[16 * kLW];  // the panel (ld kLP) while it is factored, then -Wp (ld kLW)
+  double vs[16 * kLP];  // Vp, column-major
+  double rs[16 * 128];  // the panel's factor columns, rows 0..pivot
+};
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlkNT) void k_chain_blk(ChainJobs jobs) {
+  const ChainJob& jb = jobs.job[blockIdx.x];
+  const int mode = jb.mode, w = jb.w, k = jb.k, ldx = jb.ldx, trans = jb.trans, ldo = jb.ldo;
+  double* __restrict__ X = jb.X;
+  double* __restrict__ Vout = jb.V;
+  double* __restrict__ Wout = jb.W;
+  __shared__ BlkLds S;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int mycol = 16 * wv + c;
+  auto prow = [&](int r) { return mode == 0 ? r : (w - 1 - r); };
+  auto pcol = [&](int cl) { return mode == 0 ? cl : (k - 1 - cl); };
+
+  // loads from clamped addresses, then masked (no divergent branches)
+  v4d xt[16];
+  {
+    const int cc = pcol(min(mycol, k - 1));
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * t + g + 4 * i;
+        const double x = X[tidx(prow(min(r, w - 1)), cc, ldx, trans)];
+        xt[t][i] = (r < w && mycol < k) ? x : 0.0;
+      }
+  }
+
+  const int np = (k + 15) >> 4;
+  for (int p = 0; p < np; ++p) {
+    // the owner hands its columns over in LDS (panel column-major, ld kLP)
+    if (wv == p) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S.pw[c * kLP + 16 * t + g + 4 * i] = xt[t][i];
+    }
+    __syncthreads();
+    if (wv == p) {
+      // row layout: xt[j][q] = row lane + 64 q of panel column j
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xt[j][q] = S.pw[j * kLP + lane + 64 * q];
+#pragma unroll 1
+      for (int j = 0; j < 16; ++j) {
+        const int pr = 16 * p + j;  // pivot row = logical column; the pivot column is xt[0]
+        if (pr >= k) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) S.vs[j * kLP + lane + 64 * q] = 0.0;
+        } else {
+        double ss = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double xv = (lane + 64 * q > pr) ? xt[0][q] : 0.0;
+          ss = fma(xv, xv, ss);
+        }
+        ss = wave_total(ss);
+        const double xa = (pr >= 64) ? xt[0][1] : xt[0][0];
+        const double alpha = readlane_d(xa, pr & 63);
+        double sc = 1.0, isc = 1.0;
+        if (!(ss >= 0x1.0p-900 && ss <= 0x1.0p900)) {
+          double am = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            am = fmax(am, (lane + 64 * q > pr) ? fabs(xt[0][q]) : 0.0);
+          am = wave_maxall(am);
+          sc = safe_scale(fmax(am, fabs(alpha)));
+          if (sc != 1.0) {
+            isc = (sc > 1.0) ? 0x1.0p-600 : 0x1.0p600;
+            double s2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double xv = (lane + 64 * q > pr) ? xt[0][q] * sc : 0.0;
+              s2 = fma(xv, xv, s2);
+            }
+            ss = wave_total(s2);
+          }
+        }
+        const Refl rf = make_refl_ss(alpha * sc, ss);
+        const double scal = rf.scal * sc, beta = rf.beta * isc, tau = rf.tau;
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = lane + 64 * q;
+          v[q] = (r == pr) ? 1.0 : ((r > pr) ? xt[0][q] * scal : 0.0);
+          S.vs[j * kLP + r] = v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int r = lane + 64 * q;
+          if (r <= pr) S.rs[j * 128 + r] = (r == pr) ? beta : xt[0][q];
+        }
+        double d[16];
+        d[0] = 0.0;
+#pragma unroll
+        for (int jc = 1; jc < 16; ++jc) {
+          double sd = 0.0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sd = fma(v[q], xt[jc][q], sd);
+          d[jc] = sd;
+        }
+        const double td = tau * reduce_scatter16(d, lane);
+#pragma unroll
+        for (int jc = 1; jc < 16; ++jc) {
+          const double f = readlane_d(td, 4 * jc);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) xt[jc][q] = fma(-f, v[q], xt[jc][q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xt[0][q] = tau * v[q];
+        }
+        // rotate: the next pivot column comes to xt[0]
+        const v4d t0 = xt[0];
+#pragma unroll
+        for (int i = 0; i < 15; ++i) xt[i] = xt[i + 1];
+        xt[15] = t0;
+      }
+      // -Wp for the products of the other wavefronts
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S.pw[j * kLW + lane + 64 * q] = -xt[j][q];
+    }
+    __syncthreads();
+    if (wv == p) {
+      // back to the MFMA layout: the panel's columns are now Wp
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xt[t][i] = -S.pw[c * kLW + 16 * t + g + 4 * i];
+    } else if (16 * wv < k) {
+      // C <- C - Wp (Vp^T C); Vp and Wp vanish above row 16p
+      v4d z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 64; ++s4)
+        if (s4 >= 4 * p) z = mfma4(S.vs[c * kLP + 4 * s4 + g], xt[s4 >> 2][s4 & 3], z);
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (t >= p) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc)
+            xt[t] = mfma4(S.pw[(4 * kc + g) * kLW + 16 * t + c], z[kc], xt[t]);
+        }
+    }
+    // V and factor columns of the panel to global memory
+    for (int e = tid; e < 16 * 256; e += kBlkNT) {
+      const int j = e >> 8, r = e & 255, cl = 16 * p + j;
+      if (cl < k && r < w) {
+        Vout[(size_t)prow(r) + (size_t)cl * ldo] = S.vs[j * kLP + r];
+        X[tidx(prow(r), pcol(cl), ldx, trans)] = (r <= cl) ? S.rs[j * 128 + r] : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  // W (the sizes pass through an empty asm statement so that the row masks
+  // of the loads are recomputed here rather than kept in registers)
+  int w2 = w, k2 = k;
+  __asm__ volatile("" : "+s"(w2), "+s"(k2));
+  if (16 * wv < k2 && mycol < k2) {
+    double* __restrict__ wcol = Wout + (size_t)mycol * ldo;
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * t + g + 4 * i;
+        if (r < w2) wcol[mode == 0 ? r : (w2 - 1 - r)] = xt[t][i];
+      }
+  }
+}
+
 void chain_factor_jobs(hipStream_t st, const ChainJobs& jobs) {
   if (jobs.njobs <= 0) return;
-  bool small = true;
-  for (int i = 0; i < jobs.njobs; ++i)
+  bool small = true, wide = false;
+  for (int i = 0; i < jobs.njobs; ++i) {
     small = small && jobs.job[i].k <= 64 && jobs.job[i].w <= 128;
-  if (small)
+    wide = wide || jobs.job[i].k > 64;
+  }
+  // more than 64 columns: the blocked kernel (256 x 128: 240 vs 295 us);
+  // below that its fixed cost (16-column panels, MFMA layout) does not pay
+  if (wide)
+    hipLaunchKernelGGL(k_chain_blk, dim3(jobs.njobs), dim3(kBlkNT), 0, st, jobs);
+  else if (small)
     hipLaunchKernelGGL((k_chain_reg<64>), dim3(jobs.njobs), dim3(512), 0, st, jobs);
   else
     hipLaunchKernelGGL((k_chain_reg<128>), dim3(jobs.njobs), dim3(1024), 0, st, jobs);
