@@ -6,8 +6,8 @@
 //
 // k_chain_reg: one workgroup factors one w x k tile (w <= 2 KMAX,
 // k <= KMAX) held in registers, one workgroup barrier per reflector;
-// k_chain_blk (further down) factors tiles of more than 64 columns in panels
-// of 16 with FP64 MFMA block updates.  The orthogonal factor is returned in regular WY form
+// k_chain_blk (further down) factors the larger tiles in panels of 16 columns
+// with FP64 MFMA block updates.  The orthogonal factor is returned in regular WY form
 // Qf = I - V W^T (Sec. 2.4), reflectors in the order they are computed, so
 //   QR:  tile = Qf [R; 0],   QL:  tile = Qf [0; L].
 // W is accumulated alongside the factorisation:  with Qf_i = I - V_i W_i^T,
@@ -290,10 +290,10 @@ __global__ __launch_bounds__(KMAX * 8) void k_chain_reg(ChainJobs jobs) {
 // row 16t + g + 4i of column 16wv + c, which is also the B-operand layout of
 // the k-chunks of a product over rows.  While it factors its panel, the
 // owning wavefront holds the panel in row layout instead, in the same
-// registers: xt[j][q] = row l + 64q of a panel column.  The pivot column is
-// always xt[0]: after each reflector the 16 columns rotate by one register
-// (sixteen rotations restore the order), so the reflector step is one loop
-// body rather than sixteen unrolled copies, which would not fit the
+// registers: xt[j][q] = row l + 64q of a panel column.  The reflectors run
+// four to a loop pass with pivot columns xt[0..3], after which the columns
+// rotate by four registers (four rotations restore the order): four
+// unrolled reflector steps instead of sixteen keep the loop inside the
 // instruction cache.  Reflector sums over rows are reductions over the 64
 // lanes; the 16 column sums of a reflector step are reduce-scattered
 // (v_permlane32/16_swap, then DPP mirrors) so that lane 4j ends with the
@@ -318,9 +318,25 @@ __device__ __forceinline__ void swap32(double& x, double& y) {
   y = __hiloint2double((int)hi[1], (int)lo[1]);
 }
 
+// DPP move without an old value (every lane has a source under the
+// controls used here).
+template <int CTRL>
+__device__ __forceinline__ double dpp_m(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row_total16(double x) {
+  x += dpp_m<kDppXor1>(x);
+  x += dpp_m<kDppXor2>(x);
+  x += dpp_m<kDppHalfMirror>(x);
+  x += dpp_m<kDppMirror>(x);
+  return x;
+}
+
 // Sum over all 64 lanes, in every lane.
 __device__ __forceinline__ double wave_total(double x) {
-  x = row_sum16(x);
+  x = row_total16(x);
   double y = x;
   swap16(x, y);
   x += y;
@@ -344,7 +360,7 @@ template <int CTRL>
 __device__ __forceinline__ double rs_pair(double a, double b, bool upper) {
   const double send = upper ? a : b;
   const double keep = upper ? b : a;
-  return keep + dpp_d<CTRL>(send);
+  return keep + dpp_m<CTRL>(send);
 }
 
 // d[0..15]: per-lane partial sums of 16 quantities.  Returns, in lane l, the
@@ -367,8 +383,8 @@ __device__ __forceinline__ double reduce_scatter16(double (&d)[16], int lane) {
 #pragma unroll
   for (int i = 0; i < 2; ++i) y2[i] = rs_pair<kDppMirror>(w4[i], w4[i + 2], b3);
   double z = rs_pair<kDppHalfMirror>(y2[0], y2[1], b2);
-  z += dpp_d<kDppXor2>(z);
-  z += dpp_d<kDppXor1>(z);
+  z += dpp_m<kDppXor2>(z);
+  z += dpp_m<kDppXor1>(z);
   return z;
 }
 
@@ -424,28 +440,31 @@ __global__ __launch_bounds__(kBlkNT) void k_chain_blk(ChainJobs jobs) {
       for (int j = 0; j < 16; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) xt[j][q] = S.pw[j * kLP + lane + 64 * q];
-#pragma unroll 1
-      for (int j = 0; j < 16; ++j) {
-        const int pr = 16 * p + j;  // pivot row = logical column; the pivot column is xt[0]
+      // One reflector: panel column j (logical column 16p + j) is xt[ji].
+      auto reflect = [&](const int j, const int ji) __attribute__((always_inline)) {
+        const int pr = 16 * p + j;  // pivot row = logical column
         if (pr >= k) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) S.vs[j * kLP + lane + 64 * q] = 0.0;
-        } else {
+          return;
+        }
         double ss = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double xv = (lane + 64 * q > pr) ? xt[0][q] : 0.0;
+          const double xv = (lane + 64 * q > pr) ? xt[ji][q] : 0.0;
           ss = fma(xv, xv, ss);
         }
         ss = wave_total(ss);
-        const double xa = (pr >= 64) ? xt[0][1] : xt[0][0];
+        const double xa = (pr >= 64) ? xt[ji][1] : xt[ji][0];
         const double alpha = readlane_d(xa, pr & 63);
+        // a sum of squares in [2^-900, 2^900] needs no scaling; otherwise
+        // bring the column into range by an exact power of two first
         double sc = 1.0, isc = 1.0;
         if (!(ss >= 0x1.0p-900 && ss <= 0x1.0p900)) {
           double am = 0.0;
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            am = fmax(am, (lane + 64 * q > pr) ? fabs(xt[0][q]) : 0.0);
+            am = fmax(am, (lane + 64 * q > pr) ? fabs(xt[ji][q]) : 0.0);
           am = wave_maxall(am);
           sc = safe_scale(fmax(am, fabs(alpha)));
           if (sc != 1.0) {
@@ -453,7 +472,7 @@ __global__ __launch_bounds__(kBlkNT) void k_chain_blk(ChainJobs jobs) {
             double s2 = 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const double xv = (lane + 64 * q > pr) ? xt[0][q] * sc : 0.0;
+              const double xv = (lane + 64 * q > pr) ? xt[ji][q] * sc : 0.0;
               s2 = fma(xv, xv, s2);
             }
             ss = wave_total(s2);
@@ -465,38 +484,50 @@ __global__ __launch_bounds__(kBlkNT) void k_chain_blk(ChainJobs jobs) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int r = lane + 64 * q;
-          v[q] = (r == pr) ? 1.0 : ((r > pr) ? xt[0][q] * scal : 0.0);
+          v[q] = (r == pr) ? 1.0 : ((r > pr) ? xt[ji][q] * scal : 0.0);
           S.vs[j * kLP + r] = v[q];
         }
+        // factor column: rows 0..pr (pr < 128)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int r = lane + 64 * q;
-          if (r <= pr) S.rs[j * 128 + r] = (r == pr) ? beta : xt[0][q];
+          if (r <= pr) S.rs[j * 128 + r] = (r == pr) ? beta : xt[ji][q];
         }
+        // the other 15 columns take the reflector; the pivot column becomes tau v
         double d[16];
-        d[0] = 0.0;
 #pragma unroll
-        for (int jc = 1; jc < 16; ++jc) {
+        for (int jc = 0; jc < 16; ++jc) {
           double sd = 0.0;
+          if (jc != ji) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) sd = fma(v[q], xt[jc][q], sd);
+            for (int q = 0; q < 4; ++q) sd = fma(v[q], xt[jc][q], sd);
+          }
           d[jc] = sd;
         }
         const double td = tau * reduce_scatter16(d, lane);
 #pragma unroll
-        for (int jc = 1; jc < 16; ++jc) {
+        for (int jc = 0; jc < 16; ++jc) {
+          if (jc == ji) continue;
           const double f = readlane_d(td, 4 * jc);
 #pragma unroll
           for (int q = 0; q < 4; ++q) xt[jc][q] = fma(-f, v[q], xt[jc][q]);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) xt[0][q] = tau * v[q];
-        }
-        // rotate: the next pivot column comes to xt[0]
-        const v4d t0 = xt[0];
+        for (int q = 0; q < 4; ++q) xt[ji][q] = tau * v[q];
+      };
+      // four reflectors per pass; then the columns rotate by four registers
+      // so that the next four pivot columns are xt[0..3]
+#pragma unroll 1
+      for (int j0 = 0; j0 < 16; j0 += 4) {
 #pragma unroll
-        for (int i = 0; i < 15; ++i) xt[i] = xt[i + 1];
-        xt[15] = t0;
+        for (int ji = 0; ji < 4; ++ji) reflect(j0 + ji, ji);
+        const v4d t0 = xt[0], t1 = xt[1], t2 = xt[2], t3 = xt[3];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) xt[i] = xt[i + 4];
+        xt[12] = t0;
+        xt[13] = t1;
+        xt[14] = t2;
+        xt[15] = t3;
       }
       // -Wp for the products of the other wavefronts
 #pragma unroll
@@ -553,19 +584,16 @@ __global__ __launch_bounds__(kBlkNT) void k_chain_blk(ChainJobs jobs) {
 
 void chain_factor_jobs(hipStream_t st, const ChainJobs& jobs) {
   if (jobs.njobs <= 0) return;
-  bool small = true, wide = false;
-  for (int i = 0; i < jobs.njobs; ++i) {
+  bool small = true;
+  for (int i = 0; i < jobs.njobs; ++i)
     small = small && jobs.job[i].k <= 64 && jobs.job[i].w <= 128;
-    wide = wide || jobs.job[i].k > 64;
-  }
-  // more than 64 columns: the blocked kernel (256 x 128: 240 vs 295 us);
-  // below that its fixed cost (16-column panels, MFMA layout) does not pay
-  if (wide)
-    hipLaunchKernelGGL(k_chain_blk, dim3(jobs.njobs), dim3(kBlkNT), 0, st, jobs);
-  else if (small)
+  // Tiles of at most 128 x 64: the register kernel (128 x 64: 92 vs 97 us).
+  // Larger ones: the blocked kernel (256 x 128: 221 vs 295 us for the
+  // register kernel with 128 columns; 160 x 37: 69 vs 79 us).
+  if (small)
     hipLaunchKernelGGL((k_chain_reg<64>), dim3(jobs.njobs), dim3(512), 0, st, jobs);
   else
-    hipLaunchKernelGGL((k_chain_reg<128>), dim3(jobs.njobs), dim3(1024), 0, st, jobs);
+    hipLaunchKernelGGL(k_chain_blk, dim3(jobs.njobs), dim3(kBlkNT), 0, st, jobs);
 }
 
 static void launch_chain(hipStream_t st, int mode, int w, int k, double* tile, int ldt, int trans,
