@@ -277,8 +277,17 @@ __global__ __launch_bounds__(256) void k_gemv_n_fin(int m, int nch, const double
                                                     double alpha, double beta, double* y) {
   const int row = blockIdx.x * 256 + threadIdx.x;
   if (row >= m) return;
+  // chunk order as a plain loop, eight loads in flight
   double s = 0.0;
-  for (int c = 0; c < nch; ++c) s += part[(size_t)c * m + row];
+  int c = 0;
+  for (; c + 8 <= nch; c += 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = part[(size_t)(c + u) * m + row];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += a[u];
+  }
+  for (; c < nch; ++c) s += part[(size_t)c * m + row];
   y[row] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[row]);
 }
 
@@ -390,15 +399,9 @@ __global__ __launch_bounds__(256) void k_wy_apply(int mu, int k, int nch,
     zs[t] = s;
   }
   __syncthreads();
-  if (t < k) {
-    double s = 0.0;
-    if (!transS) {
-      for (int c = t; c < k; ++c) s = fma(S[t + (size_t)c * lds], zs[c], s);
-    } else {
-      for (int c = 0; c <= t; ++c) s = fma(S[c + (size_t)t * lds], zs[c], s);
-    }
-    ys[t] = s;
-  }
+  if (t < k)
+    ys[t] = transS ? dot_in_order(S + (size_t)t * lds, 1, zs, 0, t + 1)
+                   : dot_in_order(S + t, (size_t)lds, zs, t, k);
   __syncthreads();
   const int row = blockIdx.x * 256 + t;
   if (row >= mu) return;

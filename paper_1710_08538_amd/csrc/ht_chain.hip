@@ -457,10 +457,12 @@ __global__ __launch_bounds__(kBlkNT) void k_chain_blk(ChainJobs jobs) {
         ss = wave_total(ss);
         const double xa = (pr >= 64) ? xt[ji][1] : xt[ji][0];
         const double alpha = readlane_d(xa, pr & 63);
-        // a sum of squares in [2^-900, 2^900] needs no scaling; otherwise
-        // bring the column into range by an exact power of two first
+        // a sum of squares in [2^-900, 2^900] with a pivot below 2^450 needs
+        // no scaling (the largest entry is then within [2^-454, 2^450] and
+        // alpha^2 + ss cannot overflow); otherwise bring the column into
+        // range by an exact power of two first
         double sc = 1.0, isc = 1.0;
-        if (!(ss >= 0x1.0p-900 && ss <= 0x1.0p900)) {
+        if (!(ss >= 0x1.0p-900 && ss <= 0x1.0p900 && fabs(alpha) <= 0x1.0p450)) {
           double am = 0.0;
 #pragma unroll
           for (int q = 0; q < 4; ++q)

@@ -60,6 +60,64 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return s;
 }
 
+// s = sum over c in [c0, c1) of M[c * step] * z[c], accumulated in order of c
+// (the same rounding as the plain loop) with sixteen loads in flight, so that
+// a long strided sum is not one load latency per term.
+__device__ __forceinline__ double dot_in_order(const double* __restrict__ M, size_t step,
+                                               const double* z, int c0, int c1) {
+  double s = 0.0;
+  int c = c0;
+  for (; c + 16 <= c1; c += 16) {
+    double a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] = M[(size_t)(c + u) * step];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s = fma(a[u], z[c + u], s);
+  }
+  for (; c < c1; ++c) s = fma(M[(size_t)c * step], z[c], s);
+  return s;
+}
+
+// block_sum / block_max of two values at once (two barriers instead of
+// four; each value is reduced exactly as by the single-value version).
+// `sh` must hold 2 * blockDim.x/64 doubles.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if (lane == 0) {
+    sh[wv] = a;
+    sh[nw + wv] = b;
+  }
+  __syncthreads();
+  double s = 0.0, t = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    s += sh[i];
+    t += sh[nw + i];
+  }
+  a = s;
+  b = t;
+}
+__device__ __forceinline__ void block_max2(double& a, double& b, double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_max(a);
+  b = wave_max(b);
+  __syncthreads();
+  if (lane == 0) {
+    sh[wv] = a;
+    sh[nw + wv] = b;
+  }
+  __syncthreads();
+  double s = 0.0, t = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    s = fmax(s, sh[i]);
+    t = fmax(t, sh[nw + i]);
+  }
+  a = s;
+  b = t;
+}
+
 // Counter-based N(0,1) numbers: splitmix64 (Steele, Lea, Flood 2014) feeding
 // Box-Muller; used for the zero-diagonal perturbation rho.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {

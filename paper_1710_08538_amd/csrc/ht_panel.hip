@@ -18,19 +18,28 @@ __global__ __launch_bounds__(1024) void k_house(int m, double* x, double* v, dou
                                                 double* beta_out, int overwrite) {
   __shared__ double sh[16];
   const double alpha = x[0];
-  double amax = 0.0;
-  for (int i = 1 + threadIdx.x; i < m; i += 1024) amax = fmax(amax, fabs(x[i]));
-  amax = block_max(amax, sh);
-  // exact power-of-two scaling into the safe range (tiny or huge columns)
-  const double sc = safe_scale(fmax(amax, fabs(alpha)));
   double ss = 0.0;
-  if (amax > 0.0) {
-    for (int i = 1 + threadIdx.x; i < m; i += 1024) {
-      const double t = x[i] * sc;
-      ss = fma(t, t, ss);
-    }
-  }
+  for (int i = 1 + threadIdx.x; i < m; i += 1024) ss = fma(x[i], x[i], ss);
   ss = block_sum(ss, sh);
+  // When ss >= m 2^-900, ss <= 2^880 and |alpha| <= 2^440, the largest
+  // magnitude lies in [2^-450, 2^450] and no scaling is needed (the sum is
+  // the one the scaled pass below would give with factor 1).  Otherwise scale
+  // exactly by a power of two into the safe range (tiny or huge columns).
+  double sc = 1.0;
+  if (!(ss >= (double)m * 0x1.0p-900 && ss <= 0x1.0p880 && fabs(alpha) <= 0x1.0p440)) {
+    double amax = 0.0;
+    for (int i = 1 + threadIdx.x; i < m; i += 1024) amax = fmax(amax, fabs(x[i]));
+    amax = block_max(amax, sh);
+    sc = safe_scale(fmax(amax, fabs(alpha)));
+    ss = 0.0;
+    if (amax > 0.0) {
+      for (int i = 1 + threadIdx.x; i < m; i += 1024) {
+        const double t = x[i] * sc;
+        ss = fma(t, t, ss);
+      }
+    }
+    ss = block_sum(ss, sh);
+  }
   const Refl r = make_refl_ss(alpha * sc, ss);
   const double f = sc * r.scal;
   for (int i = 1 + threadIdx.x; i < m; i += 1024) {
@@ -63,11 +72,7 @@ __global__ void k_wy_append(double* T, int ldt, int kk, const double* z, const d
   if (t < kk) zs[t] = z[t];
   __syncthreads();
   const double ta = tau[0];
-  if (t < kk) {
-    double s = 0.0;
-    for (int c = t; c < kk; ++c) s = fma(T[t + (size_t)c * ldt], zs[c], s);
-    T[t + (size_t)kk * ldt] = -ta * s;
-  }
+  if (t < kk) T[t + (size_t)kk * ldt] = -ta * dot_in_order(T + t, (size_t)ldt, zs, t, kk);
   if (t == 0) T[kk + (size_t)kk * ldt] = ta;
 }
 void wy_append(hipStream_t st, double* T, int ldt, int kk, const double* z, const double* tau) {
@@ -82,12 +87,8 @@ __global__ void k_trmv_small(int trans, int k, const double* T, int ldt, const d
   if (t < k) xs[t] = x[t];
   __syncthreads();
   if (t >= k) return;
-  double s = 0.0;
-  if (!trans) {
-    for (int c = t; c < k; ++c) s = fma(T[t + (size_t)c * ldt], xs[c], s);
-  } else {
-    for (int c = 0; c <= t; ++c) s = fma(T[c + (size_t)t * ldt], xs[c], s);
-  }
+  const double s = trans ? dot_in_order(T + (size_t)t * ldt, 1, xs, 0, t + 1)
+                         : dot_in_order(T + t, (size_t)ldt, xs, t, k);
   y[t] = alpha * s;
 }
 void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt, const double* x,
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(1024) void k_ir_residual(int m, const double* w, co
                                                       const int* Erhs, double* r, const double* x,
                                                       const double* normB, double tol_factor,
                                                       int* status, double* norms) {
-  __shared__ double sh[16];
+  __shared__ double sh[32];
   const int E = Erhs[0];
   double rmax = 0.0, xmax = 0.0;
   for (int i = threadIdx.x; i < m; i += 1024) {
@@ -116,8 +117,7 @@ __global__ __launch_bounds__(1024) void k_ir_residual(int m, const double* w, co
     rmax = fmax(rmax, fabs(ri));
     xmax = fmax(xmax, fabs(x[i]));
   }
-  rmax = block_max(rmax, sh);
-  xmax = block_max(xmax, sh);
+  block_max2(rmax, xmax, sh);
   double rs = 0.0, xs = 0.0;
   // exact power-of-two scalings (subnormal or huge entries are safe)
   const double ir = safe_scale(rmax), ix = safe_scale(xmax);
@@ -126,8 +126,7 @@ __global__ __launch_bounds__(1024) void k_ir_residual(int m, const double* w, co
     rs = fma(a, a, rs);
     xs = fma(b, b, xs);
   }
-  rs = block_sum(rs, sh);
-  xs = block_sum(xs, sh);
+  block_sum2(rs, xs, sh);
   if (threadIdx.x == 0) {
     const double rn = sqrt(rs) / ir, xn = sqrt(xs) / ix;
     norms[0] = rn;

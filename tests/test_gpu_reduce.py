@@ -126,15 +126,16 @@ def test_zero_diagonal_and_zero_B():
     assert inv["zeros_H"] == 0 and inv["bwd_A"] <= 1e-14 * n
 
 
-@pytest.mark.parametrize("e2", [-900, -600, 900])
-def test_extreme_scaling(e2):
+@pytest.mark.parametrize("e2,n,nb", [(-900, 150, 16), (-600, 150, 16), (900, 150, 16),
+                                     (-900, 400, 128), (900, 400, 128)])
+def test_extreme_scaling(e2, n, nb):
     """A and B scaled by 2^e2 (tiny or huge entries, up to 2^+-900): the
     reflectors and solves scale exactly, so H / 2^e2 and T / 2^e2 must meet
-    the invariants of the unscaled pencil."""
-    n = 150
+    the invariants of the unscaled pencil.  nb = 128 takes the chain tiles
+    through the blocked factorisation's scaled path."""
     A0, B0 = inputs.random_pencil(n, seed=21)
     f = np.ldexp(1.0, e2)
-    got, st = run_gpu(np.asfortranarray(A0 * f), np.asfortranarray(B0 * f), nb=16)
+    got, st = run_gpu(np.asfortranarray(A0 * f), np.asfortranarray(B0 * f), nb=nb)
     assert all(np.isfinite(M).all() for M in got)
     H, T, Q, Z = got
     assert_invariants(A0, B0, (H / f, T / f, Q, Z))
