@@ -200,7 +200,8 @@ constexpr int kSmallK = 256;
 __global__ __launch_bounds__(256) void k_gemv_n_small(int m, int k, double alpha,
                                                       const double* __restrict__ X, int ldx,
                                                       const double* __restrict__ x, int incx,
-                                                      double beta, double* y) {
+                                                      double beta, double* y,
+                                                      const double* __restrict__ post) {
   __shared__ double xs[kSmallK];
   for (int t = threadIdx.x; t < k; t += 256) xs[t] = x[(size_t)t * incx];
   __syncthreads();
@@ -224,7 +225,8 @@ __global__ __launch_bounds__(256) void k_gemv_n_small(int m, int k, double alpha
   }
   for (; c < k; ++c) s0 = fma(p[(size_t)c * ldx], xs[c], s0);
   const double s = (s0 + s1) + (s2 + s3);
-  y[row] = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[row]);
+  const double v = (beta == 0.0) ? alpha * s : fma(alpha, s, beta * y[row]);
+  y[row] = post ? v * post[0] : v;
 }
 
 template <bool TRI>
@@ -296,7 +298,7 @@ void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
   if (m <= 0) return;
   if (k <= kSmallK) {
     hipLaunchKernelGGL(k_gemv_n_small, dim3(cdiv(m, 256)), dim3(256), 0, st, m, k, alpha, X, ldx,
-                       x, incx, beta, y);
+                       x, incx, beta, y, (const double*)nullptr);
     return;
   }
   const int nch = cdiv(k, KC);
@@ -304,6 +306,13 @@ void gemv_n(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
                      x, incx, partials);
   hipLaunchKernelGGL(k_gemv_n_fin, dim3(cdiv(m, 256)), dim3(256), 0, st, m, nch, partials, alpha,
                      beta, y);
+}
+
+void gemv_n_small_scaled(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
+                         const double* x, double beta, double* y, const double* post) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_gemv_n_small, dim3(cdiv(m, 256)), dim3(256), 0, st, m, k, alpha, X, ldx,
+                     x, 1, beta, y, post);
 }
 
 void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x, double* y,
@@ -387,15 +396,21 @@ void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_wy_apply(int mu, int k, int nch,
                                                   const double* __restrict__ part,
+                                                  const double* __restrict__ zrow, int ldz,
                                                   const double* __restrict__ S, int lds,
                                                   int transS, double alpha,
                                                   const double* __restrict__ U, int ldu,
-                                                  double* __restrict__ xu) {
+                                                  const double* __restrict__ xin, int xoff,
+                                                  int unit, double* __restrict__ xu) {
   __shared__ double zs[128], ys[128];
   const int t = threadIdx.x;
   if (t < k) {
     double s = 0.0;
-    for (int c = 0; c < nch; ++c) s += part[(size_t)c * k + t];
+    if (zrow) {
+      s = zrow[(size_t)t * ldz];  // U^T e_unit: row `unit` of U
+    } else {
+      for (int c = 0; c < nch; ++c) s += part[(size_t)c * k + t];
+    }
     zs[t] = s;
   }
   __syncthreads();
@@ -422,12 +437,16 @@ __global__ __launch_bounds__(256) void k_wy_apply(int mu, int k, int nch,
     }
   }
   for (; c < k; ++c) s0 = fma(p[(size_t)c * ldu], ys[c], s0);
-  xu[row] = fma(alpha, (s0 + s1) + (s2 + s3), xu[row]);
+  // the vector being updated: in place, the unit vector e_unit, or [0; xin]
+  const double base = (unit >= 0) ? (row == unit ? 1.0 : 0.0)
+                      : (xin ? (row < xoff ? 0.0 : xin[row - xoff]) : xu[row]);
+  xu[row] = fma(alpha, (s0 + s1) + (s2 + s3), base);
 }
 
-void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const double* U,
-              int ldu, const double* S, int lds, bool transS, const double* xd, double* xu,
-              double* z, double* partials) {
+static void wy_apply_impl(hipStream_t st, int mu, int md, int d0, int k, double alpha,
+                          const double* U, int ldu, const double* S, int lds, bool transS,
+                          const double* xd, double* xu, double* z, double* partials,
+                          const double* xin, int xoff) {
   if (k <= 0 || mu <= 0) return;
   const int nch = md > 0 ? cdiv(md, RC) : 0;
   const double* src = partials;
@@ -439,8 +458,38 @@ void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const
     hipLaunchKernelGGL(k_gemv_t_part, dim3(k, nch), dim3(256), 0, st, md, k, U + d0, ldu, xd,
                        partials, 0, 1.0, 0.0, z);
   }
-  hipLaunchKernelGGL(k_wy_apply, dim3(cdiv(mu, 256)), dim3(256), 0, st, mu, k, nch, src, S, lds,
-                     transS ? 1 : 0, alpha, U, ldu, xu);
+  hipLaunchKernelGGL(k_wy_apply, dim3(cdiv(mu, 256)), dim3(256), 0, st, mu, k, nch, src,
+                     (const double*)nullptr, 0, S, lds, transS ? 1 : 0, alpha, U, ldu, xin, xoff,
+                     -1, xu);
+}
+
+void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const double* U,
+              int ldu, const double* S, int lds, bool transS, const double* xd, double* xu,
+              double* z, double* partials) {
+  wy_apply_impl(st, mu, md, d0, k, alpha, U, ldu, S, lds, transS, xd, xu, z, partials, nullptr,
+                0);
+}
+
+void wy_apply_padded(hipStream_t st, int mu, int md, int d0, int k, double alpha,
+                     const double* U, int ldu, const double* S, int lds, bool transS,
+                     const double* xd, double* xu, double* z, double* partials) {
+  if (k <= 0) {
+    pad_copy(st, xu, d0, xd, mu - d0);
+    return;
+  }
+  wy_apply_impl(st, mu, md, d0, k, alpha, U, ldu, S, lds, transS, xd, xu, z, partials, xd, d0);
+}
+
+void wy_apply_unit(hipStream_t st, int mu, int idx, int k, double alpha, const double* U,
+                   int ldu, const double* S, int lds, bool transS, double* xu) {
+  if (mu <= 0) return;
+  if (k <= 0) {
+    unit_vec(st, xu, mu, idx);
+    return;
+  }
+  hipLaunchKernelGGL(k_wy_apply, dim3(cdiv(mu, 256)), dim3(256), 0, st, mu, k, 0,
+                     (const double*)nullptr, U + idx, ldu, S, lds, transS ? 1 : 0, alpha, U, ldu,
+                     (const double*)nullptr, 0, idx, xu);
 }
 
 // ---------------------------------------------------------------------------

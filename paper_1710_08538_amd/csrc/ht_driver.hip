@@ -489,10 +489,15 @@ int sync_status(Ctx& c, const ColBufs& cb, int kk) {
 // Factored solve (Sec. 3.2.2 c, steps 1-3): ctil <- (I - U S U^T) ctil;
 // B ytil = 2^{-E} ctil; y <- (I - V T V^T)^T ytil.  nu = reflectors in U.
 // ---------------------------------------------------------------------------
-void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, int* Eout) {
+// unit >= 0: ctil is taken to be e_unit (not read) and formed here.
+void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, int* Eout,
+                    int unit = -1) {
   Work& w = *c.w;
   const int L = c.n - s - 1, n = c.n;
-  wy_apply(c.st, L, L, 0, nu, -1.0, w.U, n, w.S, c.nb, false, ctil, ctil, w.tk, w.partials);
+  if (unit >= 0)
+    wy_apply_unit(c.st, L, unit, nu, -1.0, w.U, n, w.S, c.nb, false, ctil);
+  else
+    wy_apply(c.st, L, L, 0, nu, -1.0, w.U, n, w.S, c.nb, false, ctil, ctil, w.tk, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRSV);
   trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout,
@@ -510,8 +515,8 @@ void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, i
 void residual(Ctx& c, int s, int kk, const double* x, const double* rhs, const ColBufs& cb) {
   Work& w = *c.w;
   const int L = c.n - s - 1, n = c.n, m = L - kk;
-  pad_copy(c.st, w.wv, kk, x, m);
-  wy_apply(c.st, L, m, kk, kk, -1.0, w.V, n, w.T, c.nb, false, x, w.wv, w.tk, w.partials);
+  wy_apply_padded(c.st, L, m, kk, kk, -1.0, w.V, n, w.T, c.nb, false, x, w.wv, w.tk,
+                  w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRMV);
   trmv_upper(c.st, L, Bp, c.ldb, w.wv, w.w2, w.partials);
@@ -751,9 +756,11 @@ int run(Ctx& c) {
       const int pi = c.prof.begin(st, HT_PROF_YGEMV);
       gemv_n(st, L, m, 1.0, at(c.A, c.lda, s + 1, j + 1), c.lda, vcol, 1, 0.0, ycol, w.partials);
       c.prof.end(st, pi, 8.0 * L * (double)m);
-      if (kk > 0) gemv_n(st, L, kk, -1.0, w.Y, n, w.tk, 1, 1.0, ycol, w.partials);
-      hipLaunchKernelGGL(k_scale_by, dim3((L + 255) / 256), dim3(256), 0, st, ycol, L,
-                         w.dscal + 5);
+      if (kk > 0)  // y = gamma (A v - Y (V^T v)), the scaling in the same launch
+        gemv_n_small_scaled(st, L, kk, -1.0, w.Y, n, w.tk, 1.0, ycol, w.dscal + 5);
+      else
+        hipLaunchKernelGGL(k_scale_by, dim3((L + 255) / 256), dim3(256), 0, st, ycol, L,
+                           w.dscal + 5);
       c.flops += 2.0 * L * (double)m + 4.0 * L * (double)kk;
     };
     // Column kk up to its first refinement verdict (posted, not read), then
@@ -775,9 +782,8 @@ int run(Ctx& c) {
       if (kk > 0) gemv_t(st, m, kk, 1.0, w.U + kk, n, ucol, 0.0, w.tk, w.partials);
       wy_append(st, w.S, nb, kk, w.tk, w.dscal + 0);
       // (c) solve B~22 x = e1 via the enlarged system
-      //   ctil = (I - U S U^T) e_kk  (computed as e_kk then the update)
-      unit_vec(st, w.ctil, L, kk);
-      factored_solve(c, s, kk, kk + 1, w.ctil, cb.ysol, cb.Erhs);
+      //   ctil = (I - U S U^T) e_kk, with U^T e_kk read as row kk of U
+      factored_solve(c, s, kk, kk + 1, w.ctil, cb.ysol, cb.Erhs, kk);
       if (kk > 0) {  // the first column of a panel is not refined (Sec. 2.3)
         residual(c, s, kk, cb.ysol + kk, nullptr, cb);
         post_status(c, cb, kk);

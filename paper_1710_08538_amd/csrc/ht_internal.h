@@ -52,6 +52,23 @@ void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const
               int ldu, const double* S, int lds, bool transS, const double* xd, double* xu,
               double* z, double* partials);
 
+// The same, with xu formed inside as [0_d0; xd] (rows 0..mu-1; xu distinct
+// from xd): one launch fewer than pad_copy + wy_apply, the same values.
+void wy_apply_padded(hipStream_t st, int mu, int md, int d0, int k, double alpha,
+                     const double* U, int ldu, const double* S, int lds, bool transS,
+                     const double* xd, double* xu, double* z, double* partials);
+
+// xu(0:mu) = e_idx + alpha U(0:mu, 0:k) op(S) U(idx, 0:k)^T: the block reflector
+// applied to a unit vector, whose U^T e_idx is row idx of U (one launch; the
+// same values as unit_vec + wy_apply).
+void wy_apply_unit(hipStream_t st, int mu, int idx, int k, double alpha, const double* U,
+                   int ldu, const double* S, int lds, bool transS, double* xu);
+
+// y(0:m) = post[0] * (alpha X(0:m, 0:k) x + beta y) for k <= 256 (one launch;
+// post is a device scalar).
+void gemv_n_small_scaled(hipStream_t st, int m, int k, double alpha, const double* X, int ldx,
+                         const double* x, double beta, double* y, const double* post);
+
 // y = B * x for upper triangular B (m x m); y and x distinct; partials as gemv_n.
 void trmv_upper(hipStream_t st, int m, const double* B, int ldb, const double* x,
                 double* y, double* partials);
