@@ -399,6 +399,19 @@ void sweep_jobs(Ctx& c, const std::vector<RJob>& jobs, int j, const Blocks& bl, 
       sa.Wp = c.w->pool[chain][1];
       sa.slot0 = w0.slot;
       sa.slot_step = wins[i + 1].slot - w0.slot;
+      {
+        // tiles of the slots that can hold nonzeros (narrow windows of early
+        // absorptions and of the Remark 3.3 blocks are zero-padded)
+        int r0 = 2 * s, r1 = 0, kx = 0;
+        for (size_t t = i; t < e; ++t) {
+          r0 = std::min(r0, wins[t].roff);
+          r1 = std::max(r1, wins[t].roff + wins[t].wdt);
+          kx = std::max(kx, wins[t].k);
+        }
+        sa.tlo = r0 / 16;
+        sa.thi = std::min(2 * s / 16, (r1 + 15) / 16);
+        sa.phi = std::min(s / 16, (kx + 15) / 16);
+      }
       double fl = 0.0;  // algorithmic: 4 rows wdt nrefl per window
       for (const RJob& jb : jobs) {
         if (jb.rows <= 0) continue;

@@ -23,6 +23,10 @@ struct SweepArgs {
   const double* Wp;   // pool of W factors
   int slot0;          // window w uses slot slot0 + w * slot_step
   int slot_step;      // (slot stride 2 k^2 doubles)
+  // Nonzero part of every slot of the run: rows [16 tlo, 16 thi) of V and W
+  // (window positions) and columns [0, 16 phi) (reflectors); products with
+  // the zero tiles outside are skipped.  0, 2k/16, k/16 for full windows.
+  int tlo, thi, phi;
 };
 
 bool sweep_supported(int k);

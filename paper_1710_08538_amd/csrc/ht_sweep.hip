@@ -161,21 +161,27 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
     v4d pt[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) pt[p] = v4d{0.0, 0.0, 0.0, 0.0};
+    // only the run's nonzero tiles of V (rows tlo..thi-1, reflectors < phi)
+    const int tlo = a.tlo, thi = a.thi, phi = a.phi;
     VReg<K> vr;
-    vr.load(V, 0, tid);
+    vr.load(V, tlo, tid);
     __syncthreads();  // the stage buffers are free
-    vr.store(stage[0], tid);
+    vr.store(stage[tlo & 1], tid);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      if (t + 1 < NT) vr.load(V, t + 1, tid);
+      if (t < tlo || t >= thi) continue;
+      if (t + 1 < thi) vr.load(V, t + 1, tid);
       const double* Vs = stage[t & 1];
+      // per accumulator the order is still t, then kc
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc)
+      for (int p = 0; p < NP; ++p) {
+        if (p >= phi) break;
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int kc = 0; kc < 4; ++kc)
           pt[p] = mfma4(Vs[(4 * kc + g) * K + 16 * p + c], xt[t][kc], pt[p]);
-      if (t + 1 < NT) vr.store(stage[(t + 1) & 1], tid);
+      }
+      if (t + 1 < thi) vr.store(stage[(t + 1) & 1], tid);
       __syncthreads();
     }
     // prefetch the columns entering the next window
@@ -192,14 +198,18 @@ __global__ __launch_bounds__(256) void k_sweep_rows(SweepArgs a) {
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      if (p + 1 < NP) wr.load(W, p + 1, tid);
+      if (p >= phi) continue;
+      if (p + 1 < phi) wr.load(W, p + 1, tid);
       const double* Ws = stage[p & 1];
+      // per accumulator the order is still p, then kc
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc)
+      for (int t = 0; t < NT; ++t) {
+        if (t < tlo || t >= thi) continue;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int kc = 0; kc < 4; ++kc)
           xt[t] = mfma4(Ws[(4 * kc + g) * 2 * K + 16 * t + c], pt[p][kc], xt[t]);
-      if (p + 1 < NP) wr.store(stage[(p + 1) & 1], tid);
+      }
+      if (p + 1 < phi) wr.store(stage[(p + 1) & 1], tid);
       __syncthreads();
     }
     // ---- advance: store the leaving half, shift the carry, take the entering half
