@@ -152,6 +152,29 @@ def test_nonfinite_input_rejected():
         htred.reduce(A, B, nb=8, check_finite=True)
 
 
+def test_profile_stats_leave_results_bitwise():
+    """HT_FLAG_PROFILE times the kernel classes with HIP events on the call's
+    stream.  Every class that runs reports launches, time and algorithmic
+    work, and the reduction is bitwise the one of the same call without
+    profiling (the events only sit between launches)."""
+    n, nb = 600, 128
+    A0, B0 = inputs.random_pencil(n, seed=31)
+    a, sa = run_gpu(A0, B0, nb=nb)
+    b, sb = run_gpu(A0, B0, nb=nb, profile=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert sa["absorptions"] == sb["absorptions"] and sa["ir_steps"] == sb["ir_steps"]
+    for c, name in enumerate(htred.PROF_CLASSES):
+        assert sb["prof_launches"][c] > 0, name
+        assert sb["prof_ms"][c] > 0.0 and sb["prof_work"][c] > 0.0, name
+    assert not any(sa["prof_launches"])
+    # the solve class's work is whole triangles of 8 L (L + 1) / 2 bytes, at
+    # most one per column and refinement step and per rolled-back column
+    t = htred.PROF_CLASSES.index("trsv")
+    per = sb["prof_work"][t] / sb["prof_launches"][t]
+    assert 8.0 * 2 * 3 / 2 <= per <= 8.0 * (n - 1) * n / 2
+
+
 def test_deterministic_bitwise():
     n = 257
     A0, B0 = inputs.random_pencil(n, seed=11)
