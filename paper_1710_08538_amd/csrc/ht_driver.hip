@@ -157,7 +157,6 @@ double* tW(Work& w, int ch, const Win& wn, int s) {
   return w.pool[ch][1] + (size_t)wn.slot * 2 * s * s + wn.roff;
 }
 
-__global__ void k_add_at(double* x, int idx, double v) { x[idx] += v; }
 __global__ void k_scale_by(double* x, int m, const double* s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) x[i] *= s[0];

@@ -46,8 +46,8 @@ void gemv_t(hipStream_t st, int m, int k, double alpha, const double* X, int ldx
 
 // xu(0:mu) += alpha U(0:mu, 0:k) op(S) (U(d0:d0+md, 0:k)^T xd) for an upper
 // triangular k x k S (k <= 128), op(S) = S^T when transS: two launches in
-// place of gemv_t + trmv_small + gemv_n.  z (k doubles) and partials are
-// scratch.
+// place of a transposed product, a small triangular product and a product.
+// z (k doubles) and partials are scratch.
 void wy_apply(hipStream_t st, int mu, int md, int d0, int k, double alpha, const double* U,
               int ldu, const double* S, int lds, bool transS, const double* xd, double* xu,
               double* z, double* partials);
@@ -95,9 +95,6 @@ void house(hipStream_t st, int m, double* x, double* v, double* tau, double* bet
 // T(kk, kk) = tau, with z (kk) on device.
 void wy_append(hipStream_t st, double* T, int ldt, int kk, const double* z,
                const double* tau);
-// y(0:k) = op(T) x for upper triangular T (k x k), scaled by alpha.
-void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt,
-                const double* x, double alpha, double* y);
 
 // Elementwise helpers.
 void fill(hipStream_t st, double* x, int m, double v);

@@ -79,25 +79,6 @@ void wy_append(hipStream_t st, double* T, int ldt, int kk, const double* z, cons
   hipLaunchKernelGGL(k_wy_append, dim3(1), dim3(128), 0, st, T, ldt, kk, z, tau);
 }
 
-// y = alpha op(T) x, T upper triangular k x k (k <= 128)
-__global__ void k_trmv_small(int trans, int k, const double* T, int ldt, const double* x,
-                             double alpha, double* y) {
-  __shared__ double xs[128];
-  const int t = threadIdx.x;
-  if (t < k) xs[t] = x[t];
-  __syncthreads();
-  if (t >= k) return;
-  const double s = trans ? dot_in_order(T + (size_t)t * ldt, 1, xs, 0, t + 1)
-                         : dot_in_order(T + t, (size_t)ldt, xs, t, k);
-  y[t] = alpha * s;
-}
-void trmv_small(hipStream_t st, bool trans, int k, const double* T, int ldt, const double* x,
-                double alpha, double* y) {
-  if (k <= 0) return;
-  hipLaunchKernelGGL(k_trmv_small, dim3(1), dim3(128), 0, st, trans ? 1 : 0, k, T, ldt, x,
-                     alpha, y);
-}
-
 // ---------------------------------------------------------------------------
 // Iterative refinement (Sec. 2.3, step c of Sec. 3.2.2).
 // r = 2^{-Erhs} c - w (c = e1 when c == NULL); status = 1 when
