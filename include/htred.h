@@ -99,6 +99,20 @@ typedef struct {
                                 ilo..n-3 are reduced; the transformations act on
                                 rows / columns ilo+1..n-1, on every row of A and
                                 B above them and on all of Q and Z. */
+    int32_t ell;             /* ht_reduce: blocks per absorption window (Sec. 3.5,
+                                accelerated reduction of V2 and U2); 0 or 2 =
+                                the basic scheme (Sec. 3.3).  l >= 3 keeps B
+                                block upper triangular between panels, with
+                                diagonal blocks of order (l-1) nb, and needs
+                                (l-1) nb <= 128.  Its solves are block back
+                                substitutions through LU decompositions with
+                                partial pivoting, without the overflow-safe
+                                scaling of the basic scheme: use it for
+                                pencils whose solves stay within the FP64
+                                range.  Zero diagonal entries of B are not
+                                perturbed (Sec. 3.2.1); an exactly singular
+                                diagonal block gets the pivot eps ||B||_F, and
+                                refinement judges the solves. */
 } ht_options;
 
 /* flags */

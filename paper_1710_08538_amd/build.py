@@ -16,7 +16,7 @@ LIB = os.path.join(OUT, "libhtred.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HTRED_ARCH", "gfx950")
 SOURCES = ["ht_blas.hip", "ht_panel.hip", "ht_trsv.hip", "ht_chain.hip", "ht_sweep.hip", "ht_driver.hip",
-           "ht_batched.hip", "ht_split.hip"]
+           "ht_batched.hip", "ht_split.hip", "ht_lu.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]

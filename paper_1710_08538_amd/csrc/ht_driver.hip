@@ -75,6 +75,8 @@ struct Work {
   // ints: [1] E_rhs, [2] E_corr, [3] status, [4] fixes, [5] scaled; [9], [11]
   // E_rhs and status of odd columns
   int *flags, *ints;
+  double* lu;  // l-block scheme: LU factors of B's diagonal blocks (N x S)
+  int* piv;    // and their pivots
   int epoch = 0;
 };
 
@@ -83,7 +85,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // slices of k x k partial sums for split-contraction WY products
 constexpr size_t kKpartSlices = 32;
 
-size_t layout(Work* w, int n, int nb, char* base) {
+// S > 0: room for the diagonal-block LU factors of the l-block scheme.
+size_t layout(Work* w, int n, int nb, char* base, int S = 0) {
   size_t off = 0;
   auto take = [&](size_t doubles) -> double* {
     double* p = base ? (double*)(base + off) : nullptr;
@@ -119,13 +122,16 @@ size_t layout(Work* w, int n, int nb, char* base) {
   w->Wk = take(N * K);
   w->partials = take(std::max<size_t>(((N + 511) / 512 + 1) * N, 64 * K));
   w->kpart = take(kKpartSlices * K * K);
-  const size_t poolsz = 2 * N * K + 4 * K * K;
+  size_t poolsz = 2 * N * K + 4 * K * K;
+  if (S > 0) poolsz = std::max(poolsz, (size_t)(S + K) * (S + K));  // l-block windows
   for (int c = 0; c < 4; ++c)
     for (int v = 0; v < 2; ++v) w->pool[c][v] = take(poolsz);
   w->Gws = take(2 * K * K + 8);
   w->dscal = take(64);
   w->flags = (int*)take(trsv_flag_bytes((int)N) / 8 + 1);
   w->ints = (int*)take(32);
+  w->lu = S > 0 ? take(N * (size_t)S) : nullptr;
+  w->piv = S > 0 ? (int*)take(N / 2 + 1) : nullptr;
   return off;
 }
 
@@ -164,6 +170,7 @@ __global__ void k_scale_by(double* x, int m, const double* s) {
 __global__ void k_count_scaled(const int* E, int* counter) {
   if (E[0] > 0) atomicAdd(counter, 1);
 }
+__global__ void k_set_int(int* p, int v) { p[0] = v; }
 __global__ void k_init_ints(int* p) {
   if (threadIdx.x < 32) p[threadIdx.x] = 0;
 }
@@ -262,6 +269,7 @@ struct Ctx {
   hipStream_t st;
   Work* w;
   int n, nb;
+  int S = 0;  // l-block scheme: diagonal block order (l - 1) nb of B; 0: basic scheme
   double *A, *B, *Q, *Z;
   int lda, ldb, ldq, ldz;
   bool wantQ, wantZ;
@@ -512,10 +520,18 @@ void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, i
     wy_apply(c.st, L, L, 0, nu, -1.0, w.U, n, w.S, c.nb, false, ctil, ctil, w.tk, w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRSV);
-  trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout,
-                    (c.opt.flags & HT_FLAG_SOLVE_SOLO) != 0);
-  c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
-  hipLaunchKernelGGL(k_count_scaled, dim3(1), dim3(1), 0, c.st, Eout, w.ints + 5);
+  if (c.S > 0) {
+    // block upper triangular B (l-block scheme, Sec. 3.5): block back
+    // substitution with the panel's LU factors, no scaling (E = 0)
+    block_solve(c.st, L, c.S, Bp, c.ldb, w.lu, n, w.piv, ctil, ysol, w.partials);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c.st, Eout, 0);
+    c.prof.end(c.st, pi, 8.0 * L * (double)(L + c.S) / 2.0);
+  } else {
+    trsv_upper_scaled(c.st, L, Bp, c.ldb, ctil, ysol, w.flags, ++w.epoch, Eout,
+                      (c.opt.flags & HT_FLAG_SOLVE_SOLO) != 0);
+    c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
+    hipLaunchKernelGGL(k_count_scaled, dim3(1), dim3(1), 0, c.st, Eout, w.ints + 5);
+  }
   if (kk > 0) {
     wy_apply(c.st, L, L, 0, kk, -1.0, w.V, n, w.T, c.nb, true, ysol, ysol, w.tk, w.partials);
   }
@@ -531,14 +547,102 @@ void residual(Ctx& c, int s, int kk, const double* x, const double* rhs, const C
                   w.partials);
   const double* Bp = at(c.B, c.ldb, s + 1, s + 1);
   const int pi = c.prof.begin(c.st, HT_PROF_TRMV);
-  trmv_upper(c.st, L, Bp, c.ldb, w.wv, w.w2, w.partials);
-  c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
+  if (c.S > 0) {
+    // block upper triangular B: a full product (the entries below the
+    // diagonal blocks are exact zeros)
+    gemv_n(c.st, L, L, 1.0, Bp, c.ldb, w.wv, 1, 0.0, w.w2, w.partials);
+    c.prof.end(c.st, pi, 8.0 * L * (double)L);
+  } else {
+    trmv_upper(c.st, L, Bp, c.ldb, w.wv, w.w2, w.partials);
+    c.prof.end(c.st, pi, 8.0 * L * (double)(L + 1) / 2.0);
+  }
   wy_apply(c.st, L, L, 0, kk + 1, -1.0, w.U, n, w.S, c.nb, true, w.w2, w.w2, w.tk, w.partials);
   ir_residual(c.st, m, w.w2 + kk, rhs, cb.Erhs, cb.rv, x, w.dscal + 2, c.opt.ir_tol_factor,
               cb.status, w.dscal + 3);
   c.flops += 1.0 * L * (double)L + 4.0 * L * (double)(2 * kk + 1);
 }
 
+
+// ---------------------------------------------------------------------------
+// Parts of an absorption common to the basic and the l-block schemes.
+// ---------------------------------------------------------------------------
+// (3.3.1 c, d, e) rank-k part of the right absorption, once V2 = [0; L1] and
+// the windows' transforms are applied.  B, Z and rows 0..s of A:
+//   W = X(:, s+1:j+1) V1 + X(:, n-k:n) L1;  X(:, s+1:j+1) -= W T V1^T;
+//   X(:, n-k:n) -= W T L1^T;
+// rows s+1..n-1 of A through Y = A V T (Sec. 3.3.1 e):
+//   A(:, j) -= Y V1(k-1,:)^T;  A(:, n-k:n) -= Y L1^T.
+void right_rank_k(Ctx& c, int s, int k) {
+  Work& w = *c.w;
+  const int n = c.n, j = s + k, L = n - s - 1;
+  double* A = c.A;
+  const int lda = c.lda;
+  struct RT { double* X; int ld; int rows; };
+  const RT rts[3] = {{c.B, c.ldb, n}, {c.wantZ ? c.Z : nullptr, c.ldz, n}, {A, lda, s + 1}};
+  const double* L1 = w.V + (L - k);
+  const double* V1 = w.V;
+  for (const RT& rt : rts) {
+    if (!rt.X || rt.rows <= 0) continue;
+    double* Xs = at(rt.X, rt.ld, 0, s + 1);
+    double* Xe = at(rt.X, rt.ld, 0, n - k);
+    wy(c, false, false, rt.rows, k, k, 1.0, Xs, rt.ld, V1, n, 0.0, w.Wk, n);
+    wy(c, false, false, rt.rows, k, k, 1.0, Xe, rt.ld, L1, n, 1.0, w.Wk, n);
+    wy(c, false, false, rt.rows, k, k, 1.0, w.Wk, n, w.T, c.nb, 0.0, w.P, n);
+    wy(c, false, true, rt.rows, k, k, -1.0, w.P, n, V1, n, 1.0, Xs, rt.ld);
+    wy(c, false, true, rt.rows, k, k, -1.0, w.P, n, L1, n, 1.0, Xe, rt.ld);
+    c.flops += 10.0 * rt.rows * (double)k * k;
+  }
+  gemv_n(c.st, L, k, -1.0, w.Y, n, w.V + (k - 1), n, 1.0, at(A, lda, s + 1, j), w.partials);
+  wy(c, false, true, L, k, k, -1.0, w.Y, n, L1, n, 1.0, at(A, lda, s + 1, n - k), lda);
+  c.flops += 4.0 * L * (double)k * k;
+}
+
+// (3.3.2 c) spike columns s+1..j of B:
+//   B(s+1:j+1, s+1:j+1) -= U1 S^T (U^T B(s+1:n, s+1:j+1));  B(j+1:n, s+1:j+1) = 0.
+void spike(Ctx& c, int s, int k) {
+  Work& w = *c.w;
+  const int n = c.n, j = s + k, L = n - s - 1, mp = n - j - 1;
+  double* B = c.B;
+  const int ldb = c.ldb;
+  wy(c, true, false, k, k, L, 1.0, w.U, n, at(B, ldb, s + 1, s + 1), ldb, 0.0, w.Kt, k);
+  wy(c, true, false, k, k, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+  wy(c, false, false, k, k, k, -1.0, w.U, n, w.Kt2, k, 1.0, at(B, ldb, s + 1, s + 1), ldb);
+  zero_mat(c.st, at(B, ldb, j + 1, s + 1), mp, k, ldb);
+  // Fact 3: columns s+1..j are now triangular; their entries below the
+  // diagonal are rounding noise of the opposite reflectors (Lemma 2.1) and are
+  // set to exact zeros, as Algorithm 2 does.
+  zero_lower(c.st, at(B, ldb, s + 1, s + 1), k, ldb, 0);
+  c.flops += 2.0 * k * (double)k * (L + 2 * k);
+}
+
+// (3.3.2 c, e) corrections with Ucat = [U1; R1] on rows s+1..j+k of B
+// (columns j+1..n-1) and A (columns j..n-1):  X -= Ucat S^T (Ucat^T X).
+void left_rank_k(Ctx& c, int s, int k) {
+  Work& w = *c.w;
+  const int n = c.n, j = s + k;
+  const int ncb = n - j - 1, nca = n - j;
+  double* Bs = at(c.B, c.ldb, s + 1, j + 1);
+  wy(c, true, false, k, ncb, 2 * k, 1.0, w.Ucat, 2 * k, Bs, c.ldb, 0.0, w.Kt, k);
+  wy(c, true, false, k, ncb, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+  wy(c, false, false, 2 * k, ncb, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, Bs, c.ldb);
+  double* As = at(c.A, c.lda, s + 1, j);
+  wy(c, true, false, k, nca, 2 * k, 1.0, w.Ucat, 2 * k, As, c.lda, 0.0, w.Kt, k);
+  wy(c, true, false, k, nca, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
+  wy(c, false, false, 2 * k, nca, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, As, c.lda);
+  c.flops += 10.0 * (double)k * k * (nca + ncb);
+}
+
+// (3.3.2 d) after Q(:, j+1:n) <- Q Q~:  W = Q(:, s+1:j+k+1) Ucat;
+// Q(:, s+1:..) -= W S Ucat^T.
+void q_rank_k(Ctx& c, int s, int k) {
+  Work& w = *c.w;
+  const int n = c.n;
+  double* Qs = at(c.Q, c.ldq, 0, s + 1);
+  wy(c, false, false, n, k, 2 * k, 1.0, Qs, c.ldq, w.Ucat, 2 * k, 0.0, w.Wk, n);
+  wy(c, false, false, n, k, k, 1.0, w.Wk, n, w.S, c.nb, 0.0, w.P, n);
+  wy(c, false, true, n, 2 * k, k, -1.0, w.P, n, w.Ucat, 2 * k, 1.0, Qs, c.ldq);
+  c.flops += 10.0 * (double)n * k * k;
+}
 
 // ---------------------------------------------------------------------------
 // Absorption of k left and right reflectors (Sec. 3.3).
@@ -593,27 +697,9 @@ void absorb(Ctx& c, int s, int k) {
     }
     sweep_jobs(c, rjobs, j, bl, 0, r0);
   }
-  const double* L1 = w.V + (L - k);
-  const double* V1 = w.V;
   copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
   copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
-
-  for (auto& rt : rts) {
-    if (rt.rows <= 0) continue;
-    double* Xs = at(rt.X, rt.ld, 0, s + 1);
-    double* Xe = at(rt.X, rt.ld, 0, n - k);
-    wy(c, false, false, rt.rows, k, k, 1.0, Xs, rt.ld, V1, n, 0.0, w.Wk, n);
-    wy(c, false, false, rt.rows, k, k, 1.0, Xe, rt.ld, L1, n, 1.0, w.Wk, n);
-    wy(c, false, false, rt.rows, k, k, 1.0, w.Wk, n, w.T, c.nb, 0.0, w.P, n);
-    wy(c, false, true, rt.rows, k, k, -1.0, w.P, n, V1, n, 1.0, Xs, rt.ld);
-    wy(c, false, true, rt.rows, k, k, -1.0, w.P, n, L1, n, 1.0, Xe, rt.ld);
-    c.flops += 10.0 * rt.rows * (double)k * k;
-  }
-  // rows s+1..n-1 of A through Y = A V T (Sec. 3.3.1 e):
-  //   A(:, j+1:n) <- A Q^;  A(:, j) -= Y V1(k-1,:)^T;  A(:, n-k:n) -= Y L1^T.
-  gemv_n(c.st, L, k, -1.0, w.Y, n, w.V + (k - 1), n, 1.0, at(A, lda, s + 1, j), w.partials);
-  wy(c, false, true, L, k, k, -1.0, w.Y, n, L1, n, 1.0, at(A, lda, s + 1, n - k), lda);
-  c.flops += 4.0 * L * (double)k * k;
+  right_rank_k(c, s, k);
 
   // (3.3.1 e) restore B by RQ decompositions, bottom to top: the k x (w)
   // block of row block b_t is factored as [0 R] G_t; G_t^T is applied to
@@ -632,43 +718,17 @@ void absorb(Ctx& c, int s, int k) {
     sweep_jobs(c, jobs, j, bl, 1, right_windows(bl, 1));
   }
 
-  // (3.3.2 c) spike columns s+1..j of B:
-  //   B(s+1:j+1, s+1:j+1) -= U1 S^T (U^T B(s+1:n, s+1:j+1));  B(j+1:n, s+1:j+1) = 0.
-  wy(c, true, false, k, k, L, 1.0, w.U, n, at(B, ldb, s + 1, s + 1), ldb, 0.0, w.Kt, k);
-  wy(c, true, false, k, k, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
-  wy(c, false, false, k, k, k, -1.0, w.U, n, w.Kt2, k, 1.0, at(B, ldb, s + 1, s + 1), ldb);
-  zero_mat(c.st, at(B, ldb, j + 1, s + 1), mp, k, ldb);
-  // Fact 3: columns s+1..j are now triangular; their entries below the
-  // diagonal are rounding noise of the opposite reflectors (Lemma 2.1) and are
-  // set to exact zeros, as Algorithm 2 does.
-  zero_lower(c.st, at(B, ldb, s + 1, s + 1), k, ldb, 0);
-  c.flops += 2.0 * k * (double)k * (L + 2 * k);
+  spike(c, s, k);
 
   // (3.3.2 c, e) rows j+1..n-1: B(:, j+1:n) and A(:, j:n) <- Q~^T (.)
   sweep_jobs(c, {RJob{at(B, ldb, 0, j + 1), ldb, n - j - 1, true, j + 1},
                  RJob{at(A, lda, 0, j), lda, n - j, false, j}},
              j, bl, 2, left_windows(bl, 2), true);
-  // corrections with Ucat = [U1; R1] on rows s+1..j+k:  X -= Ucat S^T (Ucat^T X)
-  {
-    const int ncb = n - j - 1, nca = n - j;
-    double* Bs = at(B, ldb, s + 1, j + 1);
-    wy(c, true, false, k, ncb, 2 * k, 1.0, w.Ucat, 2 * k, Bs, ldb, 0.0, w.Kt, k);
-    wy(c, true, false, k, ncb, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
-    wy(c, false, false, 2 * k, ncb, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, Bs, ldb);
-    double* As = at(A, lda, s + 1, j);
-    wy(c, true, false, k, nca, 2 * k, 1.0, w.Ucat, 2 * k, As, lda, 0.0, w.Kt, k);
-    wy(c, true, false, k, nca, k, 1.0, w.S, c.nb, w.Kt, k, 0.0, w.Kt2, k);
-    wy(c, false, false, 2 * k, nca, k, -1.0, w.Ucat, 2 * k, w.Kt2, k, 1.0, As, lda);
-    c.flops += 10.0 * (double)k * k * (nca + ncb);
-  }
-  // (3.3.2 d) Q(:, j+1:n) <- Q Q~;  W = Q(:, s+1:j+k+1) Ucat;  Q(:, s+1:..) -= W S Ucat^T.
+  left_rank_k(c, s, k);
+  // (3.3.2 d) Q(:, j+1:n) <- Q Q~, then the Ucat correction
   if (c.wantQ) {
     sweep_cols_right(c, c.Q, c.ldq, n, j, bl, 2);
-    double* Qs = at(c.Q, c.ldq, 0, s + 1);
-    wy(c, false, false, n, k, 2 * k, 1.0, Qs, c.ldq, w.Ucat, 2 * k, 0.0, w.Wk, n);
-    wy(c, false, false, n, k, k, 1.0, w.Wk, n, w.S, c.nb, 0.0, w.P, n);
-    wy(c, false, true, n, 2 * k, k, -1.0, w.P, n, w.Ucat, 2 * k, 1.0, Qs, c.ldq);
-    c.flops += 10.0 * (double)n * k * k;
+    q_rank_k(c, s, k);
   }
 
   // (3.3.2 f) restore B by QR decompositions, top to bottom; each H_t^T is
@@ -684,6 +744,135 @@ void absorb(Ctx& c, int s, int k) {
   }
   sweep_left(c, A, lda, j, false, j, bl, 3);
   if (c.wantQ) sweep_cols_right(c, c.Q, c.ldq, n, j, bl, 3);
+}
+
+// ---------------------------------------------------------------------------
+// Absorption with l >= 3 blocks (Sec. 3.5, accelerated reduction of V2 and
+// U2).  B's trailing part is kept block upper triangular with diagonal
+// blocks of order S = (l - 1) nb aligned at its bottom (ell_bounds; the top
+// block holds the remainder), so the chains have one window per diagonal
+// block (S + k rows) instead of one per nb rows, and each restoring step
+// clears only the k-wide fill next to a block with k reflectors:
+//   right: the first k rows of the orthogonal factor of the RQ decomposition
+//     of the block's rows over the window's columns, reduced by an LQ
+//     decomposition (the 2nb x 3nb construction for l = 3, k = nb);
+//   left: the last k columns of the orthogonal factor of the QR
+//     decomposition of the block's columns over its rows and the k rows
+//     below, reduced by a QL decomposition.
+// Every window's transform is applied at once, by general products, to B, A
+// and Z (right) or B, A and Q (left).  The entries that a restoring step
+// clears are set to exact zeros, so that the solves and residuals of the
+// next panel see B's block structure exactly.
+// ---------------------------------------------------------------------------
+std::vector<int> ell_bounds(int m, int S) {
+  std::vector<int> b{0};
+  if (m <= 0) return b;
+  if (m <= S) {
+    b.push_back(m);
+    return b;
+  }
+  const int p = m % S ? m % S : S;
+  for (int e = p; e <= m; e += S) b.push_back(e);
+  return b;
+}
+
+void absorb_ell(Ctx& c, int s, int k) {
+  Work& w = *c.w;
+  const int n = c.n, j = s + k, mp = n - j - 1, S = c.S;
+  double *A = c.A, *B = c.B;
+  const int lda = c.lda, ldb = c.ldb;
+  c.absorptions++;
+  const std::vector<int> bd = ell_bounds(mp, S);
+  const int nblk = (int)bd.size() - 1;
+  const int ldo = S + c.nb;  // rows of every window and restoring block
+  double *Vw = w.pool[0][0], *Ww = w.pool[0][1];    // chain window (k reflectors)
+  double *V1 = w.pool[1][0], *W1 = w.pool[1][1];    // restoring RQ / QR (block order)
+  double *V2r = w.pool[2][0], *W2r = w.pool[2][1];  // its k-reflector reduction
+  double *Ct = w.pool[3][0], *Mt = w.pool[3][1];    // copies and the factor's block
+  double* V2 = w.V + k;
+  copy_mat(c.st, mp, k, w.U + k, n, w.Ucp, n);
+
+  // (3.3.1 b, c) V2 -> [0; L1] by QL windows from the top, one per diagonal
+  // block with the rows carried from the window above; each window's
+  // transform goes at once to B (rows above the window's end), A and Z.
+  std::vector<int> carry_r(nblk, 0);
+  {
+    int carry = 0;
+    for (int i = 0; i < nblk; ++i) {
+      const int ws = bd[i] - carry, we = bd[i + 1], rows = we - ws;
+      carry_r[i] = carry;
+      carry = std::min(k, rows);
+      if (i == 0 && nblk > 1 && rows <= k) continue;  // a small top block is carried whole
+      chain(c, 1, false, rows, k, V2 + ws, n, Vw, Ww, ldo);
+      right_apply(c, at(B, ldb, 0, j + 1 + ws), ldb, j + 1 + we, rows, k, Vw, Ww, ldo);
+      right_apply(c, at(A, lda, 0, j + 1 + ws), lda, n, rows, k, Vw, Ww, ldo);
+      if (c.wantZ) right_apply(c, at(c.Z, c.ldz, 0, j + 1 + ws), c.ldz, n, rows, k, Vw, Ww, ldo);
+    }
+  }
+  right_rank_k(c, s, k);
+
+  // (3.3.1 e) back to block upper triangular form, bottom block first: for
+  // block i, C = B(block rows, window columns) = R Q (RQ through the QL
+  // decomposition of C^T = Qf [0; L], Q = Qf^T); the first `cr` columns of
+  // Qf, E1 - V1 W1(0:cr, :)^T, are reduced by a QR decomposition Qf2 [R2; 0],
+  // and C Qf2 has zero first cr columns.
+  for (int i = nblk - 1; i >= 1; --i) {
+    const int cr = carry_r[i];
+    if (cr <= 0) continue;
+    const int a = bd[i], e = bd[i + 1], z = e - a, ws = a - cr, wdt = z + cr;
+    double* C = at(B, ldb, j + 1 + a, j + 1 + ws);
+    copy_mat(c.st, z, wdt, C, ldb, Ct, ldo);
+    chain(c, 1, true, wdt, z, Ct, ldo, V1, W1, ldo);
+    zero_mat(c.st, Mt, wdt, cr, ldo);
+    set_identity(c.st, Mt, cr, ldo);
+    gemm(c.st, false, true, wdt, cr, z, -1.0, V1, ldo, W1, ldo, 1.0, Mt, ldo);
+    chain(c, 0, false, wdt, cr, Mt, ldo, V2r, W2r, ldo);
+    right_apply(c, at(B, ldb, 0, j + 1 + ws), ldb, j + 1 + e, wdt, cr, V2r, W2r, ldo);
+    right_apply(c, at(A, lda, 0, j + 1 + ws), lda, n, wdt, cr, V2r, W2r, ldo);
+    if (c.wantZ) right_apply(c, at(c.Z, c.ldz, 0, j + 1 + ws), c.ldz, n, wdt, cr, V2r, W2r, ldo);
+    zero_mat(c.st, C, z, cr, ldb);
+  }
+
+  spike(c, s, k);
+
+  // (3.3.2 b, c, d) U2 -> [R1; 0] by QR windows from the bottom, aligned with
+  // the tops of the diagonal blocks; each goes at once to B (columns j+1..),
+  // A (columns j..) and Q.
+  {
+    int carry = 0;
+    for (int i = nblk - 1; i >= 0; --i) {
+      const int ws = bd[i], we = bd[i + 1] + carry, rows = we - ws;
+      carry = std::min(k, rows);
+      chain(c, 0, false, rows, k, w.Ucp + ws, n, Vw, Ww, ldo);
+      left_apply(c, at(B, ldb, j + 1 + ws, j + 1), ldb, mp, rows, k, Vw, Ww, ldo);
+      left_apply(c, at(A, lda, j + 1 + ws, j), lda, n - j, rows, k, Vw, Ww, ldo);
+      if (c.wantQ) right_apply(c, at(c.Q, c.ldq, 0, j + 1 + ws), c.ldq, n, rows, k, Vw, Ww, ldo);
+    }
+  }
+  copy_mat(c.st, k, k, w.U, n, w.Ucat, 2 * k);
+  copy_mat(c.st, k, k, w.Ucp, n, w.Ucat + k, 2 * k);
+  left_rank_k(c, s, k);
+  if (c.wantQ) q_rank_k(c, s, k);
+
+  // (3.3.2 f) back to block upper triangular form, top block first: for
+  // block i and the k rows below it, C = B(rows, block columns) = Qf [R; 0];
+  // the last k columns of Qf, E_last - V1 W1(z:z+k, :)^T, are reduced by a QL
+  // decomposition Qf3 [0; L3], and Qf3^T C has zero last k rows.
+  for (int i = 0; i + 1 < nblk; ++i) {
+    const int a = bd[i], e = bd[i + 1], z = e - a, cr = std::min(k, mp - e), wdt = z + cr;
+    if (cr <= 0) continue;
+    double* C = at(B, ldb, j + 1 + a, j + 1 + a);
+    copy_mat(c.st, wdt, z, C, ldb, Ct, ldo);
+    chain(c, 0, false, wdt, z, Ct, ldo, V1, W1, ldo);
+    zero_mat(c.st, Mt, wdt, cr, ldo);
+    set_identity(c.st, Mt + z, cr, ldo);
+    gemm(c.st, false, true, wdt, cr, z, -1.0, V1, ldo, W1 + z, ldo, 1.0, Mt, ldo);
+    chain(c, 1, false, wdt, cr, Mt, ldo, V2r, W2r, ldo);
+    left_apply(c, C, ldb, mp - a, wdt, cr, V2r, W2r, ldo);
+    left_apply(c, at(A, lda, j + 1 + a, j), lda, n - j, wdt, cr, V2r, W2r, ldo);
+    if (c.wantQ) right_apply(c, at(c.Q, c.ldq, 0, j + 1 + a), c.ldq, n, wdt, cr, V2r, W2r, ldo);
+    zero_mat(c.st, at(B, ldb, j + 1 + e, j + 1 + a), cr, z, ldb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -749,8 +938,11 @@ int run(Ctx& c) {
   while (s <= n - 3) {
     const int L = n - s - 1;
     const int kmax = std::min(std::min(nb, n - 2 - s), L / 2);
-    fix_diagonal(st, c.B, c.ldb, s + 1, n, w.dscal + 2, c.opt.seed, (uint64_t)panel + 1,
-                 w.ints + 4);
+    if (c.S > 0)  // block upper triangular B: LU of its diagonal blocks, once per panel
+      lu_blocks(st, L, c.S, at(c.B, c.ldb, s + 1, s + 1), c.ldb, w.lu, n, w.piv, w.dscal + 2);
+    else
+      fix_diagonal(st, c.B, c.ldb, s + 1, n, w.dscal + 2, c.opt.seed, (uint64_t)panel + 1,
+                   w.ints + 4);
     zero_mat(st, w.U, L, nb, n);
     zero_mat(st, w.V, L, nb, n);
     zero_mat(st, w.S, nb, nb, nb);
@@ -862,7 +1054,8 @@ int run(Ctx& c) {
       pending = kk++;
     }
     if (k == 0) return HT_ERR_HIP;  // cannot happen: the first column never refines
-    absorb(c, s, k);
+    if (c.S > 0) absorb_ell(c, s, k);
+    else absorb(c, s, k);
     s += k;
     ++panel;
   }
@@ -891,8 +1084,12 @@ int ht_default_options(ht_options* opt) {
   opt->seed = 0x5EEDull;
   opt->batch_block = 32;
   opt->batch_wg_per_cu = 3;
+  opt->ell = 2;
   return 0;
 }
+
+// Diagonal block order of B in the l-block scheme (0: basic scheme).
+static int ell_stride(const ht_options& o) { return o.ell > 2 ? (o.ell - 1) * o.nb : 0; }
 
 static int resolve_opts(const ht_options* in, ht_options* out) {
   ht_default_options(out);
@@ -909,6 +1106,8 @@ static int resolve_opts(const ht_options* in, ht_options* out) {
   if (out->batch_block < 1 || out->batch_block > 64) return -10;
   if (out->batch_wg_per_cu < 1 || out->batch_wg_per_cu > 3) return -10;
   if (out->ilo < 0) return -10;
+  if (out->ell == 0) out->ell = 2;
+  if (out->ell < 2 || (out->ell > 2 && (out->ell - 1) * out->nb > 128)) return -10;
   if (out->prec < HT_PREC_FP64 || out->prec > HT_PREC_SPLIT_FP8) return -10;
   if (out->prec != HT_PREC_FP64) {
     const int fmt = out->prec == HT_PREC_SPLIT_BF16 ? 0 : 1;
@@ -922,7 +1121,7 @@ size_t ht_workspace_size(int64_t n, const ht_options* opt) {
   ht_options o;
   if (resolve_opts(opt, &o) != 0 || n < 0 || n > (1 << 30)) return 0;
   Work w;
-  return layout(&w, (int)n, o.nb, nullptr) + 256;
+  return layout(&w, (int)n, o.nb, nullptr, ell_stride(o)) + 256;
 }
 
 }  // extern "C"
@@ -956,9 +1155,9 @@ int scratch_ptr(char** out) {
 
 // Bytes of the device workspace for order n, panel width nb, including the
 // finite-scan flag at its end.
-size_t workspace_need(int n, int nb) {
+size_t workspace_need(int n, int nb, int S = 0) {
   Work w;
-  return layout(&w, n, nb, nullptr) + 256;
+  return layout(&w, n, nb, nullptr, S) + 256;
 }
 
 // The common body of ht_reduce and ht_reduce_noalloc.  `ws` is the device
@@ -989,7 +1188,7 @@ int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t l
   if (n == 0) return 0;
 
   const int ni = (int)n;
-  const size_t need = workspace_need(ni, o.nb);
+  const size_t need = workspace_need(ni, o.nb, ell_stride(o));
   char* base = ws;
   bool owned = false;
   if (base) {
@@ -1040,7 +1239,7 @@ int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t l
     owned = true;
   }
   Work w;
-  layout(&w, ni, o.nb, base);
+  layout(&w, ni, o.nb, base, ell_stride(o));
   (void)hipMemsetAsync(w.flags, 0, trsv_flag_bytes(ni), st);
 
   Ctx c;
@@ -1048,6 +1247,7 @@ int reduce_impl(double* A, double* B, double* Q, double* Z, int64_t n, int64_t l
   c.w = &w;
   c.n = ni;
   c.nb = o.nb;
+  c.S = ell_stride(o);
   c.A = A; c.B = B; c.Q = Q; c.Z = Z;
   c.lda = (int)lda; c.ldb = (int)ldb; c.ldq = (int)ldq; c.ldz = (int)ldz;
   c.wantQ = wantQ;
@@ -1167,7 +1367,8 @@ int ht_reduce_noalloc(double* A, double* B, double* Q, double* Z, int64_t n, int
   const int orc = resolve_opts(opt, &o);
   if (orc) return orc;
   if (n < 0 || n > (int64_t)1 << 30) return -5;
-  if (n > 0 && workspace_need((int)n, o.nb) > kScratchBytes) return HT_ERR_TOO_LARGE;
+  if (n > 0 && workspace_need((int)n, o.nb, ell_stride(o)) > kScratchBytes)
+    return HT_ERR_TOO_LARGE;
   char* p = nullptr;
   if (n > 0) {
     const int src = scratch_ptr(&p);

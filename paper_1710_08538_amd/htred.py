@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
                 ("n_slices", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("ir_tol_factor", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("batch_block", ctypes.c_int32), ("batch_wg_per_cu", ctypes.c_int32),
-                ("ilo", ctypes.c_int32)]
+                ("ilo", ctypes.c_int32), ("ell", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -161,7 +161,7 @@ def _qz(X, mode, n, like, name):
 
 
 def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, check_finite,
-                 profile, solve_solo, qmode, zmode, ilo=0):
+                 profile, solve_solo, qmode, zmode, ilo=0, ell=2):
     n = A.shape[0]
     lda, ldb = _ld(A, n, "A"), _ld(B, n, "B")
     Q, ldq = _qz(Q, qmode, n, A, "Q")
@@ -170,7 +170,7 @@ def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, ch
         from paper_1710_08538_amd import autotune
         nb = autotune.pick_nb(n)
     o = options(nb=nb, max_ir=max_ir, ir_tol_factor=ir_tol_factor, seed=seed, prec=prec,
-                n_slices=n_slices, qmode=qmode, zmode=zmode, ilo=ilo,
+                n_slices=n_slices, qmode=qmode, zmode=zmode, ilo=ilo, ell=ell,
                 flags=(HT_FLAG_CHECK_FINITE if check_finite else 0)
                 | (HT_FLAG_PROFILE if profile else 0)
                 | (HT_FLAG_SOLVE_SOLO if solve_solo else 0))
@@ -182,7 +182,7 @@ def _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices, ch
 def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
            prec=HT_PREC_FP64, n_slices=0, stats=False, workspace=None, stream=None,
            check_finite=False, profile=False, solve_solo=False, qmode=HT_QZ_IDENTITY,
-           zmode=HT_QZ_IDENTITY, ilo=0):
+           zmode=HT_QZ_IDENTITY, ilo=0, ell=2):
     """In-place HouseHT reduction: A -> H, B -> T; returns (Q, Z[, stats]).
 
     A, B: n x n column-major float64 GPU tensors (B upper triangular).
@@ -195,9 +195,11 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
     solve_solo: run every triangular solve on one workgroup (testing).
     ilo: first column to reduce (columns before it already final, e.g. after
         preprocess()).
+    ell: blocks per absorption window; 2 = the basic scheme, >= 3 the
+        accelerated absorption with block upper triangular B ((ell-1) nb <= 128).
     """
     Q, Z, o, ptrs = _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices,
-                                 check_finite, profile, solve_solo, qmode, zmode, ilo)
+                                 check_finite, profile, solve_solo, qmode, zmode, ilo, ell)
     st = Stats()
     ws_ptr, ws_bytes = None, 0
     if workspace is not None:

@@ -56,6 +56,25 @@ def test_workspace_size_grows_with_n(L):
     assert L.ht_workspace_size(1000, ctypes.byref(bad)) == 0
 
 
+def test_ell_option(L):
+    """l-block absorption (Sec. 3.5): 0 and 2 are the basic scheme; l >= 3
+    needs (l - 1) nb <= 128 and adds the diagonal-block LU area (n x (l-1) nb
+    doubles and n pivots) to the workspace."""
+    from paper_1710_08538_amd import htred
+    o = htred.Options()
+    L.ht_default_options(ctypes.byref(o))
+    assert o.ell == 2
+    n = 1000
+    base = L.ht_workspace_size(n, ctypes.byref(htred.options(nb=64)))
+    assert L.ht_workspace_size(n, ctypes.byref(htred.options(nb=64, ell=0))) == base
+    e3 = L.ht_workspace_size(n, ctypes.byref(htred.options(nb=64, ell=3)))
+    assert e3 >= base + 8 * n * 128 + 4 * n
+    assert L.ht_workspace_size(n, ctypes.byref(htred.options(nb=32, ell=5))) > 0
+    for bad in (dict(nb=128, ell=3), dict(nb=64, ell=4), dict(nb=32, ell=6), dict(ell=1),
+                dict(ell=-1)):
+        assert L.ht_workspace_size(n, ctypes.byref(htred.options(**bad))) == 0, bad
+
+
 def test_argument_validation_without_device(L):
     from paper_1710_08538_amd import htred
     o = htred.options()
