@@ -289,6 +289,9 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the order (same generator)")
     ap.add_argument("--nb", type=int, default=128)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "bf16", "fp8"])
+    ap.add_argument("--ell", type=int, default=2,
+                    help="blocks per absorption window: 2 basic scheme, >= 3 the "
+                         "accelerated absorption with block triangular B")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -323,7 +326,8 @@ def main():
     B = htred.colmajor_empty(n)
     Q = htred.colmajor_empty(n)
     Z = htred.colmajor_empty(n)
-    ws = torch.empty(htred.workspace_size(n, nb=args.nb), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(htred.workspace_size(n, nb=args.nb, ell=args.ell), dtype=torch.uint8,
+                     device="cuda")
     torch.cuda.synchronize()
     log("inputs resident on the device")
 
@@ -331,7 +335,7 @@ def main():
         A.copy_(A0d)
         B.copy_(B0d)
         return htred.reduce(A, B, Q, Z, nb=args.nb, prec=prec, stats=True, workspace=ws,
-                            profile=profile)[2]
+                            profile=profile, ell=args.ell)[2]
 
     t = time.time()
     step(False)
@@ -429,7 +433,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if fp64 else ("f64-split-" + args.prec),
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "nb": args.nb,
+        "config": {"workload": args.workload, "n": n, "nb": args.nb, "ell": args.ell,
                    "generator": inputs.WORKLOADS[args.workload][0],
                    "flop_model": "39 n^3 nominal"},
         "steps_requested": args.steps,

@@ -86,13 +86,14 @@ size_t trsv_flag_bytes(int m);
 // Block upper triangular B (l-block absorption): LU decompositions with
 // partial pivoting of the diagonal blocks of the trailing L x L part (order
 // S <= 128, aligned at its bottom) into lu (L x S, leading dimension ldlu)
-// and piv (L ints); then x = B^{-1} c by block back substitution with those
-// factors (x distinct from c; partials as gemv_n).  An exactly zero pivot
-// column gets the pivot eps ||B||_F (normB on device).
+// and perm (L ints: each block's row permutation); then x = B^{-1} c by
+// block back substitution with those factors (x distinct from c; partials as
+// gemv_n).  An exactly zero pivot column gets the pivot eps ||B||_F (normB
+// on device).
 void lu_blocks(hipStream_t st, int L, int S, const double* B, int ldb, double* lu, int ldlu,
-               int* piv, const double* normB);
+               int* perm, const double* normB);
 void block_solve(hipStream_t st, int L, int S, const double* B, int ldb, const double* lu,
-                 int ldlu, const int* piv, const double* c, double* x, double* partials);
+                 int ldlu, const int* perm, const double* c, double* x, double* partials);
 
 // Householder reflector (LAPACK convention): for x of length m at `x`,
 // v (written to `v`, v[0] = 1) and tau with (I - tau v v^T) x = beta e1,

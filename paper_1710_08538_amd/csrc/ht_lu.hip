@@ -6,7 +6,8 @@
 // The diagonal blocks of the trailing L x L matrix have order S and are
 // aligned at its bottom: block i (from the bottom) is [max(0, L - (i+1) S),
 // L - i S).  Factors live in an L x S area `lu` (column q of block [a, e) at
-// lu + a + q ld) with the pivots, 0-based within the block, at piv + a.
+// lu + a + q ld); the row permutation of the pivoting, 0-based within the
+// block (row r of P x is x[perm[r]]), at perm + a.
 #include <algorithm>
 
 #include "ht_device.h"
@@ -22,10 +23,11 @@ constexpr int kLuNT = 256;
 // pivot eps * ||B||_F (the solves then carry an error that refinement sees).
 __global__ __launch_bounds__(kLuNT) void k_lu_blocks(int L, int S, const double* __restrict__ B,
                                                      int ldb, double* __restrict__ lu, int ldlu,
-                                                     int* __restrict__ piv,
+                                                     int* __restrict__ perm,
                                                      const double* __restrict__ normB) {
   __shared__ double sval[kLuNT];
   __shared__ int sidx[kLuNT];
+  __shared__ int spiv[128];
   const int e = L - (int)blockIdx.x * S;
   if (e <= 0) return;
   const int a = max(0, e - S), z = e - a, tid = threadIdx.x;
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(kLuNT) void k_lu_blocks(int L, int S, const double*
       __syncthreads();
     }
     const int pr = sidx[0];
-    if (tid == 0) piv[a + c] = pr;
+    if (tid == 0) spiv[c] = pr;
     if (pr != c)
       for (int q = tid; q < z; q += kLuNT) {
         const double t = F[c + (size_t)q * ldlu];
@@ -72,50 +74,111 @@ __global__ __launch_bounds__(kLuNT) void k_lu_blocks(int L, int S, const double*
     }
     __syncthreads();
   }
+  // the interchanges, applied in order to the identity, as one permutation
+  if (tid == 0) {
+    for (int r = 0; r < z; ++r) sidx[r] = r;
+    for (int c = 0; c < z; ++c) {
+      const int t = sidx[c];
+      sidx[c] = sidx[spiv[c]];
+      sidx[spiv[c]] = t;
+    }
+  }
+  __syncthreads();
+  if (tid < z) perm[a + tid] = sidx[tid];
 }
 
-// x(a:a+z) <- U^{-1} L^{-1} P x(a:a+z) with the factors of one block.
-__global__ __launch_bounds__(kLuNT) void k_lu_solve(const double* __restrict__ lu, int ldlu,
-                                                    const int* __restrict__ piv, int a, int z,
-                                                    double* __restrict__ x) {
-  __shared__ double xs[128];
-  const int tid = threadIdx.x;
+// x(a:a+z) <- U^{-1} L^{-1} P x(a:a+z) with the factors of one block: one
+// wavefront, lane l holding rows l and l + 64; each substitution step
+// broadcasts the finished entry from its lane.  The factor columns are read
+// in chunks of kCh, the next chunk's loads issued before the current chunk
+// is used, so that the serial steps do not wait on memory; the row indexes
+// of the loads are clamped into the block (unused rows are masked).
+constexpr int kCh = 16;
+
+__device__ __forceinline__ void lu_load_cols(const double* __restrict__ F, int ldlu, int q0,
+                                             int q1, int cfirst, int z, double f0[kCh],
+                                             double f1[kCh]) {
+#pragma unroll
+  for (int u = 0; u < kCh; ++u) {
+    const int c = min(max(cfirst + u, 0), z - 1);
+    f0[u] = F[q0 + (size_t)c * ldlu];
+    f1[u] = F[q1 + (size_t)c * ldlu];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_lu_solve(const double* __restrict__ lu, int ldlu,
+                                                 const int* __restrict__ perm, int a, int z,
+                                                 double* __restrict__ x) {
+  const int r0 = threadIdx.x, r1 = threadIdx.x + 64;
+  const int q0 = min(r0, z - 1), q1 = min(r1, z - 1);
   const double* F = lu + a;
-  if (tid < z) xs[tid] = x[a + tid];
-  __syncthreads();
-  if (tid == 0)
-    for (int c = 0; c < z; ++c) {
-      const int p = piv[a + c];
-      const double t = xs[c];
-      xs[c] = xs[p];
-      xs[p] = t;
+  double v0 = r0 < z ? x[a + perm[a + r0]] : 0.0;
+  double v1 = r1 < z ? x[a + perm[a + r1]] : 0.0;
+  const double rd0 = 1.0 / F[q0 + (size_t)q0 * ldlu], rd1 = 1.0 / F[q1 + (size_t)q1 * ldlu];
+  double f0[kCh], f1[kCh], g0[kCh], g1[kCh];
+  // forward substitution with the unit lower factor, columns ascending
+  lu_load_cols(F, ldlu, q0, q1, 0, z, f0, f1);
+  for (int c0 = 0; c0 < z; c0 += kCh) {
+    if (c0 + kCh < z) lu_load_cols(F, ldlu, q0, q1, c0 + kCh, z, g0, g1);
+#pragma unroll
+    for (int u = 0; u < kCh; ++u) {
+      const int c = c0 + u;
+      if (c < z) {
+        const double xc = c < 64 ? __shfl(v0, c) : __shfl(v1, c - 64);
+        if (r0 > c && r0 < z) v0 -= f0[u] * xc;
+        if (r1 > c && r1 < z) v1 -= f1[u] * xc;
+      }
     }
-  __syncthreads();
-  for (int c = 0; c < z; ++c) {
-    const double xc = xs[c];
-    if (tid > c && tid < z) xs[tid] -= F[tid + (size_t)c * ldlu] * xc;
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kCh; ++u) {
+      f0[u] = g0[u];
+      f1[u] = g1[u];
+    }
   }
-  for (int c = z - 1; c >= 0; --c) {
-    const double xc = xs[c] / F[c + (size_t)c * ldlu];
-    __syncthreads();
-    if (tid < c) xs[tid] -= F[tid + (size_t)c * ldlu] * xc;
-    if (tid == c) xs[c] = xc;
-    __syncthreads();
+  // back substitution with the upper factor, columns descending: chunk
+  // [c0 - kCh + 1, c0], entry u at column c0 - u
+  auto load_desc = [&](int chi, double h0[kCh], double h1[kCh]) {
+#pragma unroll
+    for (int u = 0; u < kCh; ++u) {
+      const int c = min(max(chi - u, 0), z - 1);
+      h0[u] = F[q0 + (size_t)c * ldlu];
+      h1[u] = F[q1 + (size_t)c * ldlu];
+    }
+  };
+  load_desc(z - 1, f0, f1);
+  for (int c0 = z - 1; c0 >= 0; c0 -= kCh) {
+    if (c0 - kCh >= 0) load_desc(c0 - kCh, g0, g1);
+#pragma unroll
+    for (int u = 0; u < kCh; ++u) {
+      const int c = c0 - u;
+      if (c >= 0) {
+        const double xc = c < 64 ? __shfl(v0 * rd0, c) : __shfl(v1 * rd1, c - 64);
+        if (r0 < c) v0 -= f0[u] * xc;
+        if (r1 < c) v1 -= f1[u] * xc;
+        if (r0 == c) v0 = xc;
+        if (r1 == c) v1 = xc;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kCh; ++u) {
+      f0[u] = g0[u];
+      f1[u] = g1[u];
+    }
   }
-  if (tid < z) x[a + tid] = xs[tid];
+  if (r0 < z) x[a + r0] = v0;
+  if (r1 < z) x[a + r1] = v1;
 }
 
 void lu_blocks(hipStream_t st, int L, int S, const double* B, int ldb, double* lu, int ldlu,
-               int* piv, const double* normB) {
+               int* perm, const double* normB) {
   if (L <= 0 || S <= 0 || S > 128) return;
   const int nblk = (L + S - 1) / S;
-  hipLaunchKernelGGL(k_lu_blocks, dim3(nblk), dim3(kLuNT), 0, st, L, S, B, ldb, lu, ldlu, piv,
+  hipLaunchKernelGGL(k_lu_blocks, dim3(nblk), dim3(kLuNT), 0, st, L, S, B, ldb, lu, ldlu, perm,
                      normB);
 }
 
 void block_solve(hipStream_t st, int L, int S, const double* B, int ldb, const double* lu,
-                 int ldlu, const int* piv, const double* c, double* x, double* partials) {
+                 int ldlu, const int* perm, const double* c, double* x, double* partials) {
   if (L <= 0 || S <= 0 || S > 128) return;
   copy(st, x, c, L);
   for (int e = L; e > 0; e -= S) {
@@ -123,7 +186,7 @@ void block_solve(hipStream_t st, int L, int S, const double* B, int ldb, const d
     if (e < L)
       gemv_n(st, z, L - e, -1.0, B + (size_t)a + (size_t)e * ldb, ldb, x + e, 1, 1.0, x + a,
              partials);
-    hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(kLuNT), 0, st, lu, ldlu, piv, a, z, x);
+    hipLaunchKernelGGL(k_lu_solve, dim3(1), dim3(64), 0, st, lu, ldlu, perm, a, z, x);
   }
 }
 

@@ -399,8 +399,8 @@ def check(A0, B0, H, T, Q, Z, stream=None):
     return {"bwd_A": out[0], "bwd_B": out[1], "orth_Q": out[2], "orth_Z": out[3]}
 
 
-def workspace_size(n, nb=64):
-    return lib().ht_workspace_size(n, ctypes.byref(options(nb=nb)))
+def workspace_size(n, nb=64, ell=2):
+    return lib().ht_workspace_size(n, ctypes.byref(options(nb=nb, ell=ell)))
 
 
 def version():
