@@ -64,3 +64,37 @@ def test_ell_n1000_matches_oracle_and_basic_scheme():
     d = checks.compare(got2, got3, A0, B0)
     assert max(d[k] for k in ("max_H", "max_T", "max_Q", "max_Z")) <= TOL, d
     assert st3["columns"] == st2["columns"] == n - 2
+
+
+def test_ell_with_split_precision_products():
+    """The l-block scheme with its window products in the BF16 precision form
+    meets the FP64 bars (the products go through the same WY-update path)."""
+    from paper_1710_08538_amd import htred
+    n = 300
+    A0, B0 = inputs.random_pencil(n, seed=n + 17)
+    got, st = run_gpu(A0, B0, nb=32, ell=3, prec=htred.HT_PREC_SPLIT_BF16)
+    assert_invariants(A0, B0, got)
+    assert_parity(oracle.ms_ht(A0, B0), got, A0, B0)
+
+
+def test_ell_after_zero_column_preprocessing():
+    """ht_preprocess, then the l-block reduction from column ilo."""
+    from oracle import preprocess
+    from paper_1710_08538_amd import htred
+    from test_gpu_front import _bars_ok, _dev, _host, _residuals
+    n, ell0, nb = 300, 20, 32
+    A0, B0 = inputs.zero_column_pencil(n, ell0, seed=n)
+    print("ht_preprocess + ht_reduce(ilo, ell=3) n=%d" % n, flush=True)
+    A, B = _dev(A0), _dev(B0)
+    Q, Z, ilo = htred.preprocess(A, B, nb=nb)
+    assert ilo == ell0
+    htred.reduce(A, B, Q, Z, nb=nb, ilo=ilo, ell=3, qmode=htred.HT_QZ_ACCUMULATE,
+                 zmode=htred.HT_QZ_ACCUMULATE)
+    got = _host(A, B, Q, Z)
+    assert not np.any(np.tril(got[0], -2)) and not np.any(np.tril(got[1], -1))
+    r = _residuals(A0, B0, *got)
+    assert _bars_ok(r, n), r
+    ref = preprocess.preprocessed_ht(A0, B0)
+    d = checks.compare_ilo(ref[:4], got, A0, B0, ell0)
+    for key in ("max_H", "max_T", "max_Q", "max_Z"):
+        assert d[key] <= TOL, (key, d)
