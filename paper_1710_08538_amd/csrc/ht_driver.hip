@@ -76,7 +76,7 @@ struct Work {
   // E_rhs and status of odd columns
   int *flags, *ints;
   double* lu;  // l-block scheme: LU factors of B's diagonal blocks (N x S)
-  int* piv;    // and their pivots
+  int* perm;   // and their row permutations
   int epoch = 0;
 };
 
@@ -131,7 +131,7 @@ size_t layout(Work* w, int n, int nb, char* base, int S = 0) {
   w->flags = (int*)take(trsv_flag_bytes((int)N) / 8 + 1);
   w->ints = (int*)take(32);
   w->lu = S > 0 ? take(N * (size_t)S) : nullptr;
-  w->piv = S > 0 ? (int*)take(N / 2 + 1) : nullptr;
+  w->perm = S > 0 ? (int*)take(N / 2 + 1) : nullptr;
   return off;
 }
 
@@ -523,7 +523,7 @@ void factored_solve(Ctx& c, int s, int kk, int nu, double* ctil, double* ysol, i
   if (c.S > 0) {
     // block upper triangular B (l-block scheme, Sec. 3.5): block back
     // substitution with the panel's LU factors, no scaling (E = 0)
-    block_solve(c.st, L, c.S, Bp, c.ldb, w.lu, n, w.piv, ctil, ysol, w.partials);
+    block_solve(c.st, L, c.S, Bp, c.ldb, w.lu, n, w.perm, ctil, ysol, w.partials);
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c.st, Eout, 0);
     c.prof.end(c.st, pi, 8.0 * L * (double)(L + c.S) / 2.0);
   } else {
@@ -939,7 +939,7 @@ int run(Ctx& c) {
     const int L = n - s - 1;
     const int kmax = std::min(std::min(nb, n - 2 - s), L / 2);
     if (c.S > 0)  // block upper triangular B: LU of its diagonal blocks, once per panel
-      lu_blocks(st, L, c.S, at(c.B, c.ldb, s + 1, s + 1), c.ldb, w.lu, n, w.piv, w.dscal + 2);
+      lu_blocks(st, L, c.S, at(c.B, c.ldb, s + 1, s + 1), c.ldb, w.lu, n, w.perm, w.dscal + 2);
     else
       fix_diagonal(st, c.B, c.ldb, s + 1, n, w.dscal + 2, c.opt.seed, (uint64_t)panel + 1,
                    w.ints + 4);
