@@ -117,3 +117,68 @@ def test_block_solve_pivots():
     B = np.array([[0.0, 1.0, 2.0], [1.0, 0.0, 3.0], [0.0, 0.0, 5.0]])
     x = eb.block_solve(B, [0, 2, 3], np.array([1.0, 2.0, 5.0]))
     assert np.allclose(x, [-1.0, -1.0, 1.0], rtol=0, atol=1e-15)
+
+
+# Planted mistakes: each plausible slip in the geometry must fail a pin above.
+
+def _pins_right(m=41, s=8, k=4):
+    test_right_pass(m, s, k)
+
+
+def _pins_left(m=41, s=8, k=4):
+    test_left_pass(m, s, k)
+
+
+def test_planted_windows_without_carry_fail(monkeypatch):
+    """V2 windows that cover only their own block (no rows carried from the
+    window above) leave V2 unreduced."""
+    def no_carry(bounds, k):
+        return [(a, e, 0) for a, e in zip(bounds[:-1], bounds[1:])]
+    monkeypatch.setattr(eb, "right_windows", no_carry)
+    with pytest.raises(AssertionError):
+        _pins_right()
+
+
+def test_planted_lq_of_the_wrong_rows_fails(monkeypatch):
+    """Reducing the last instead of the first k rows of the RQ factor does
+    not clear the fill."""
+    def wrong_rows(C, c):
+        import scipy.linalg
+        _, Q = scipy.linalg.rq(C)
+        Q2, _ = np.linalg.qr(Q[-c:, :].T, mode="complete")
+        return Q2
+    monkeypatch.setattr(eb, "clear_leading_columns", wrong_rows)
+    with pytest.raises(AssertionError):
+        _pins_right()
+
+
+def test_planted_ql_replaced_by_qr_fails(monkeypatch):
+    """A QR instead of a QL decomposition of the factor's last k columns does
+    not clear the k rows below a block."""
+    def qr_instead(C, c):
+        w, z = C.shape
+        Q, _ = np.linalg.qr(C, mode="complete")
+        Q3, _ = np.linalg.qr(Q[:, z:], mode="complete")
+        return Q3
+    monkeypatch.setattr(eb, "clear_trailing_rows", qr_instead)
+    with pytest.raises(AssertionError):
+        _pins_left()
+
+
+def test_planted_bounds_aligned_at_the_top_fail(monkeypatch):
+    """Blocks aligned at the top (remainder at the bottom) break the U2
+    windows' alignment with the tops of the diagonal blocks of a B built
+    with bottom-aligned blocks."""
+    true_bounds = eb.block_bounds
+
+    def top_aligned(m, s):
+        if m <= s:
+            return [0, m]
+        return list(range(0, m, s)) + [m]
+    rng = np.random.default_rng(3)
+    m, s, k = 41, 8, 4
+    B, bounds = block_upper(m, s, rng)  # bottom-aligned blocks
+    monkeypatch.setattr(eb, "block_bounds", top_aligned)
+    B1, _, _, _ = eb.left_pass(B, rng.standard_normal((m, k)), k, s)
+    assert true_bounds(m, s) != top_aligned(m, s)
+    assert eb.below_blocks_max(B1, bounds) > 1e-3
