@@ -216,12 +216,12 @@ def reduce(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EE
 def reduce_noalloc(A, B, Q=None, Z=None, nb=64, max_ir=10, ir_tol_factor=2.0, seed=0x5EED,
                    prec=HT_PREC_FP64, n_slices=0, stats=False, stream=None,
                    check_finite=False, solve_solo=False, qmode=HT_QZ_IDENTITY,
-                   zmode=HT_QZ_IDENTITY):
+                   zmode=HT_QZ_IDENTITY, ilo=0, ell=2):
     """ht_reduce_noalloc: as reduce(), with the library's fixed device
     scratch in place of a workspace (no allocation inside the call; pass Q
     and Z to keep this wrapper from allocating them)."""
     Q, Z, o, ptrs = _reduce_args(A, B, Q, Z, nb, max_ir, ir_tol_factor, seed, prec, n_slices,
-                                 check_finite, False, solve_solo, qmode, zmode)
+                                 check_finite, False, solve_solo, qmode, zmode, ilo, ell)
     st = Stats()
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     rc = lib().ht_reduce_noalloc(*ptrs, ctypes.byref(o), ctypes.byref(st) if stats else None,
